@@ -1,0 +1,177 @@
+/*
+ * qai.h -- C ABI of libqai, the MI355X (gfx950) implementation of the
+ * quantization-aware interpolation (QAI) decompression post-pass of
+ * Jiao et al., "Mitigating Artifacts in Pre-quantization Based Scientific
+ * Data Compressors with Quantization-aware Interpolation" (arXiv 2602.20097).
+ *
+ * The header is HIP-free: device pointers are plain pointers and a stream is
+ * a hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Data layout (every entry point): a field is a dense row-major FP32 array of
+ * dims = {nz, ny, nx}, x fastest (the paper's Q[i,j,k] with k innermost,
+ * Algorithm 2).  A 2-D field is {1, ny, nx}; a 1-D field {1, 1, nx}.  Each
+ * extent must lie in [1, QAI_MAX_EXTENT].
+ *
+ * Error convention: every entry point returns QAI_OK (0) or a negative code.
+ * Argument errors are detected on the host before anything is enqueued.
+ * Launch failures return QAI_EHIP; qai_last_error() gives the text (per
+ * thread).  Faults inside kernels surface at the caller's next
+ * synchronisation, as HIP reports them.  Nothing aborts and nothing throws.
+ *
+ * Determinism: results are bit-identical across runs, launch shapes and
+ * autotuner choices.  Calls are reentrant when their workspaces differ.
+ */
+#ifndef QAI_H
+#define QAI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QAI_MAX_EXTENT 16384
+
+enum {
+    QAI_OK = 0,
+    QAI_EINVAL = -1, /* null pointer, non-finite or non-positive bound/parameter */
+    QAI_EDIMS = -2,  /* an extent outside [1, QAI_MAX_EXTENT] */
+    QAI_ENOWS = -3,  /* workspace missing or smaller than qai_workspace_bytes() */
+    QAI_EHIP = -4,   /* a HIP runtime call or kernel launch failed */
+    QAI_ENODEV = -5, /* no usable GPU */
+    QAI_ESTATE = -6  /* object used in a state that does not allow the call */
+};
+
+/* Device status bits reported by qai_device_status() after a run. */
+#define QAI_STATUS_QRANGE 0x1u /* some |x'/(2 eb)| > 2^21 or not finite: output unspecified */
+
+/* Interpolation parameters (Section V, step E).  eta is the boundary
+ * magnitude factor (the paper uses 0.9); power is the inverse-distance
+ * exponent p of w = k1^-p / (k1^-p + k2^-p) (the paper's weight is p = 1).
+ * flags: QAI_FLAG_KEEP_D2 keeps the second EDT's words in the workspace
+ * (4 more bytes written per voxel), which qai_backward needs. */
+typedef struct {
+    float eta;
+    float power;
+    uint32_t flags;
+} qai_params;
+
+#define QAI_FLAG_KEEP_D2 0x1u
+
+/* Optional per-voxel intermediates, each a device array of N = nz*ny*nx
+ * entries or NULL:
+ *   q     recovered quantization index (Eq. 1)
+ *   b1    1 on a quantization boundary B1 (Algorithm 2), else 0
+ *   sb    boundary sign S_B in {-1, 0, +1} (Algorithm 2), 0 off B1
+ *   s     propagated sign S (Algorithm 3)
+ *   d1sq  squared distance to B1 (step B), -1 when B1 is empty
+ *   b2    1 on a sign-flipping boundary B2 (Algorithm 3), else 0
+ *   d2sq  squared distance to B2 (step D), -1 when B2 is empty
+ *   w     interpolation weight in [0, 1] (step E) */
+typedef struct {
+    int32_t* q;
+    uint8_t* b1;
+    int8_t* sb;
+    int8_t* s;
+    int32_t* d1sq;
+    uint8_t* b2;
+    int32_t* d2sq;
+    float* w;
+} qai_taps;
+
+/* qai_mitigate -- the whole post-pass, Algorithm 4 (Distance-Based
+ * Compensation): out = field + C, C = w * S * eta * eb, with the default
+ * parameters eta = 0.9, p = 1.
+ *   field  device FP32[N], the decompressed data x' = 2 eb q (Eq. 1); the
+ *          indices q are recovered as rintf(field / (2 eb)) and must satisfy
+ *          |q| <= 2^21 (else QAI_STATUS_QRANGE is raised, see below)
+ *   dims   host int64[3] = {nz, ny, nx}
+ *   eb     absolute error bound used by the pre-quantization (> 0, finite)
+ *   out    device FP32[N]; may equal field (in place), may not partly overlap
+ *   stream hipStream_t or NULL
+ * Allocates and frees its workspace stream-ordered (hipMallocAsync); callers
+ * that must not allocate use qai_mitigate_ex. */
+int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out, void* stream);
+
+/* Bytes of device workspace qai_mitigate_ex needs for dims: two 32-bit words
+ * per voxel plus a 64 KiB header (status word, reduction partials).  0 for
+ * invalid dims. */
+size_t qai_workspace_bytes(const int64_t dims[3]);
+
+/* qai_mitigate_ex -- as qai_mitigate with explicit parameters (NULL = the
+ * defaults), a caller-owned device workspace ws of ws_bytes >=
+ * qai_workspace_bytes(dims) (any alignment of 256 bytes or more), and optional
+ * taps (NULL = none).  With QAI_FLAG_KEEP_D2 the workspace afterwards holds
+ * the two distance words per voxel that qai_backward consumes; keep it
+ * untouched until then. */
+int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const qai_params* params,
+                    void* ws, size_t ws_bytes, float* out, const qai_taps* taps, void* stream);
+
+/* qai_backward -- adjoint of step E (project addition, not in the paper).
+ * The EDTs are piecewise constant in the data and are held fixed, so
+ *   d out / d field = identity            (grad_field = grad_out, not written)
+ *   dL/d eta   = sum_i g_i * w_i * S_i * eb
+ *   dL/d power = sum_i g_i * S_i * eta * eb * (-w_i (1 - w_i) ln(k1_i / k2_i))
+ * (0 wherever w is pinned at 0 or 1).
+ *   grad_out     device FP32[N], dL/d out
+ *   ws_saved     the workspace of the qai_mitigate_ex call (made with
+ *                QAI_FLAG_KEEP_D2) being differentiated; its header is reused
+ *                for the partial sums
+ *   grad_params  device FP32[2] receiving {dL/d eta, dL/d power} (overwritten)
+ * The reduction is deterministic (fixed tree, FP64 partial sums). */
+int qai_backward(const float* grad_out, void* ws_saved, size_t ws_bytes, const int64_t dims[3],
+                 float eb, const qai_params* params, float* grad_params, void* stream);
+
+/* qai_device_status -- synchronises stream and reports the status bits the
+ * last run on workspace ws raised (QAI_STATUS_*). */
+int qai_device_status(const void* ws, void* stream, uint32_t* flags);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char* qai_last_error(void);
+
+/* ------------------------------------------------------------------ batch
+ * Batched form (project addition, not in the paper): many fields of uneven
+ * shapes in one persistent kernel, captured once in a hipGraph and replayed.
+ * Each field's result is bit-identical to qai_mitigate_ex on it alone. */
+typedef struct qai_batch_plan qai_batch_plan;
+
+/* Bytes of device workspace a batch of n fields needs. */
+size_t qai_batch_workspace_bytes(int n, const int64_t (*dims)[3]);
+
+/* Build a plan: validates every field, uploads a descriptor table into ws,
+ * and captures the persistent launch into a graph on stream.  fields/outs
+ * are arrays of n device pointers, dims n host triples, ebs n host floats.
+ * The plan keeps the raw pointers until qai_batch_plan_destroy. */
+int qai_batch_plan_create(int n, const float* const* fields, const int64_t (*dims)[3], const float* ebs,
+                          float* const* outs, const qai_params* params, void* ws, size_t ws_bytes,
+                          void* stream, qai_batch_plan** plan);
+
+/* Replay the captured graph on stream (hipGraphLaunch). */
+int qai_batch_plan_launch(qai_batch_plan* plan, void* stream);
+
+/* Run the same batch without the graph, as one launch per stage per field
+ * (the reference point the persistent form is compared with). */
+int qai_batch_plan_launch_per_field(qai_batch_plan* plan, void* stream);
+
+void qai_batch_plan_destroy(qai_batch_plan* plan);
+
+/* ------------------------------------------------------------ utilities */
+
+/* Plain device copy of n 32-bit words (a bandwidth probe: the achievable HBM
+ * rate that the post-pass is compared with). */
+int qai_copy_probe(const void* src, void* dst, size_t n_words, void* stream);
+
+/* Per-stage timing of qai_mitigate_ex calls: when enabled, every call records
+ * HIP events around each kernel on the caller's stream; qai_stage_times()
+ * synchronises, adds the elapsed milliseconds of each stage since the last
+ * reset into ms[0..n-1] and reports the stage count. names (nullable) receives
+ * static strings. */
+int qai_profile_enable(int on);
+int qai_stage_times(double* ms, const char** names, int n, int* n_stages, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAI_H */

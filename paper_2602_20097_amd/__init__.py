@@ -1,0 +1,192 @@
+"""MI355X-native quantization-aware interpolation (QAI) post-pass.
+
+A from-scratch gfx950 implementation of the decompression post-pass of Jiao
+et al., "Mitigating Artifacts in Pre-quantization Based Scientific Data
+Compressors with Quantization-aware Interpolation" (arXiv 2602.20097),
+Algorithm 4.  Every step runs in the HIP kernels of ``libqai.so``; this module
+only marshals torch tensors (device memory, the current stream) into the C
+ABI of ``include/qai.h``.
+
+    import torch, paper_2602_20097_amd as qai
+    out = qai.mitigate(x_dec_cuda_f32, eb)                 # Algorithm 4
+    out, taps = qai.mitigate(x_dec, eb, taps=True)         # with intermediates
+    y = qai.QAIFunction.apply(x_dec, eta_t, power_t, eb)    # differentiable
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import QAIError, QAI_STATUS_QRANGE  # noqa: F401
+
+__all__ = ["mitigate", "workspace_bytes", "device_status", "backward", "QAIFunction", "fit_params",
+           "copy_probe", "profile", "stage_times", "QAIError", "lib"]
+
+
+def lib():
+    return _lib.load()
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_field(t, name="field"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return _lib.dims3(t.shape)
+
+
+def workspace_bytes(shape):
+    return int(lib().qai_workspace_bytes(_lib.dims3(shape)))
+
+
+def new_workspace(shape, device=None):
+    """A 256-byte aligned uint8 device tensor large enough for ``shape``."""
+    n = workspace_bytes(shape)
+    if n == 0:
+        raise QAIError(-2, f"invalid shape {tuple(shape)}")
+    return torch.empty(n, dtype=torch.uint8, device=device or "cuda")
+
+
+_TAP_TYPES = dict(q=torch.int32, b1=torch.uint8, sb=torch.int8, s=torch.int8, d1sq=torch.int32,
+                  b2=torch.uint8, d2sq=torch.int32, w=torch.float32)
+
+
+def mitigate(field, eb, eta=0.9, power=1.0, *, taps=False, out=None, workspace=None, keep_d2=False,
+             stream=None):
+    """Run the QAI post-pass on a decompressed float32 CUDA tensor.
+
+    ``eb`` is the absolute error bound of the pre-quantization (Eq. 1).
+    Returns ``out`` or, with ``taps=True``, ``(out, dict_of_intermediates)``
+    (``q``, ``b1``, ``sb``, ``s``, ``d1sq``, ``b2``, ``d2sq``, ``w``).
+    ``workspace`` (optional) is a uint8 device tensor of at least
+    ``workspace_bytes(field.shape)`` bytes; ``keep_d2`` keeps the distances
+    the adjoint needs in it.
+    """
+    L = lib()
+    dims = _check_field(field)
+    if out is None:
+        out = torch.empty_like(field)
+    else:
+        _check_field(out, "out")
+        if out.shape != field.shape:
+            raise ValueError("out has the wrong shape")
+    if workspace is None:
+        workspace = new_workspace(field.shape, field.device)
+    tp = None
+    tap_t = {}
+    if taps:
+        tap_t = {k: torch.empty(field.shape, dtype=v, device=field.device) for k, v in _TAP_TYPES.items()}
+        tp = _lib.Taps(**{k: v.data_ptr() for k, v in tap_t.items()})
+    prm = _lib.Params(float(eta), float(power), _lib.QAI_FLAG_KEEP_D2 if keep_d2 else 0)
+    rc = L.qai_mitigate_ex(ctypes.c_void_p(field.data_ptr()), dims, ctypes.c_float(eb), ctypes.byref(prm),
+                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                           ctypes.c_void_p(out.data_ptr()), ctypes.byref(tp) if tp is not None else None,
+                           _stream_ptr(stream))
+    _lib.check(rc)
+    return (out, tap_t) if taps else out
+
+
+def mitigate_simple(field, eb, out=None, stream=None):
+    """The allocate-inside entry point ``qai_mitigate`` (default parameters)."""
+    L = lib()
+    dims = _check_field(field)
+    if out is None:
+        out = torch.empty_like(field)
+    _lib.check(L.qai_mitigate(ctypes.c_void_p(field.data_ptr()), dims, ctypes.c_float(eb),
+                              ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def device_status(workspace, stream=None):
+    flags = ctypes.c_uint32(0)
+    _lib.check(lib().qai_device_status(ctypes.c_void_p(workspace.data_ptr()), _stream_ptr(stream),
+                                       ctypes.byref(flags)))
+    return int(flags.value)
+
+
+def backward(grad_out, workspace, shape, eb, eta=0.9, power=1.0, stream=None):
+    """Adjoint of step E: returns a float32 CUDA tensor ``[dL/deta, dL/dpower]``
+    for a workspace filled by ``mitigate(..., keep_d2=True)``."""
+    L = lib()
+    _check_field(grad_out, "grad_out")
+    g = torch.empty(2, dtype=torch.float32, device=grad_out.device)
+    prm = _lib.Params(float(eta), float(power), 0)
+    _lib.check(L.qai_backward(ctypes.c_void_p(grad_out.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                              workspace.numel(), _lib.dims3(shape), ctypes.c_float(eb), ctypes.byref(prm),
+                              ctypes.c_void_p(g.data_ptr()), _stream_ptr(stream)))
+    return g
+
+
+class QAIFunction(torch.autograd.Function):
+    """Differentiable QAI (project addition): ``y = QAIFunction.apply(x_dec,
+    eta, power, eb)`` with ``eta`` and ``power`` 0-dim float32 tensors.  The
+    distance transforms are held fixed; gradients flow to the decompressed
+    values (identity) and to ``eta`` and ``power``."""
+
+    @staticmethod
+    def forward(ctx, x_dec, eta, power, eb):
+        ws = new_workspace(x_dec.shape, x_dec.device)
+        e, p = float(eta), float(power)
+        out = mitigate(x_dec.detach().contiguous(), eb, e, p, workspace=ws, keep_d2=True)
+        ctx.save_for_backward(ws)
+        ctx.meta = (tuple(x_dec.shape), float(eb), e, p, eta.dtype, power.dtype)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (ws,) = ctx.saved_tensors
+        shape, eb, e, p, edt, pdt = ctx.meta
+        g = backward(grad_out.contiguous().float(), ws, shape, eb, e, p)
+        return grad_out, g[0].to(edt), g[1].to(pdt), None
+
+
+def fit_params(x_dec, x_orig, eb, steps=50, eta0=0.9, power0=1.0, lr=0.05, fit_power=True):
+    """Fit eta (and optionally the IDW power) for one field by minimising the
+    MSE between the compensated and the original data with Adam.  Returns
+    ``(eta, power, history_of_mse)``."""
+    eta = torch.tensor(float(eta0), device=x_dec.device, requires_grad=True)
+    pw = torch.tensor(float(power0), device=x_dec.device, requires_grad=fit_power)
+    opt = torch.optim.Adam([eta, pw] if fit_power else [eta], lr=lr)
+    hist = []
+    for _ in range(steps):
+        opt.zero_grad()
+        y = QAIFunction.apply(x_dec, eta, pw, eb)
+        loss = torch.mean((y - x_orig) ** 2)
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            pw.clamp_(min=0.05)
+        hist.append(float(loss.detach()))
+    return float(eta.detach()), float(pw.detach()), hist
+
+
+def copy_probe(src, dst, stream=None):
+    """Device copy of ``src`` into ``dst`` (same number of bytes, multiple of 4)."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n or n % 4:
+        raise ValueError("copy_probe needs equal sizes that are multiples of 4 bytes")
+    _lib.check(lib().qai_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n // 4,
+                                    _stream_ptr(stream)))
+
+
+def profile(on=True):
+    _lib.check(lib().qai_profile_enable(1 if on else 0))
+
+
+def stage_times(reset=True):
+    """Milliseconds per stage accumulated since the last reset (synchronises)."""
+    L = lib()
+    ms = (ctypes.c_double * 32)()
+    names = (ctypes.c_char_p * 32)()
+    k = ctypes.c_int(0)
+    _lib.check(L.qai_stage_times(ms, names, 32, ctypes.byref(k), 1 if reset else 0))
+    return {names[i].decode(): ms[i] for i in range(min(k.value, 32))}

@@ -1,0 +1,348 @@
+// qai_api.hip -- the C ABI of libqai: argument validation, workspace layout,
+// stream-ordered dispatch of the post-pass, status and error reporting,
+// stage timing and the bandwidth probe.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "qai.h"
+#include "qai_device.h"
+#include "qai_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char* what)
+{
+    return fail(QAI_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kHeader = 64 * 1024;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int check_dims(const int64_t dims[3], int64_t* n)
+{
+    if (!dims)
+        return fail(QAI_EINVAL, "dims is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || dims[a] > QAI_MAX_EXTENT)
+            return fail(QAI_EDIMS, "extent %d = %lld outside [1, %d]", a, (long long)dims[a], QAI_MAX_EXTENT);
+    *n = dims[0] * dims[1] * dims[2];
+    return QAI_OK;
+}
+
+int check_eb(float eb)
+{
+    if (!(eb > 0.0f) || !isfinite(eb))
+        return fail(QAI_EINVAL, "error bound must be finite and > 0 (got %g)", (double)eb);
+    const float two = 2.0f * eb, inv = 1.0f / two;
+    if (!isfinite(two) || !isfinite(inv) || !(inv > 0.0f))
+        return fail(QAI_EINVAL, "error bound %g out of the representable range", (double)eb);
+    return QAI_OK;
+}
+
+int check_params(const qai_params* p, qai_params* out)
+{
+    qai_params d = {0.9f, 1.0f, 0u};
+    if (p)
+        d = *p;
+    if (!isfinite(d.eta))
+        return fail(QAI_EINVAL, "eta must be finite");
+    if (!isfinite(d.power) || !(d.power > 0.0f))
+        return fail(QAI_EINVAL, "power must be finite and > 0");
+    *out = d;
+    return QAI_OK;
+}
+
+// ---- stage timing
+struct StageRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<StageRec> g_pending;
+std::vector<std::pair<const char*, double>> g_acc;
+thread_local hipEvent_t g_cur_a = nullptr;
+thread_local const char* g_cur_name = nullptr;
+
+} // namespace
+
+namespace qai {
+
+void prof_begin(const char* name, hipStream_t s)
+{
+    if (!g_prof_on)
+        return;
+    hipEvent_t a;
+    if (hipEventCreate(&a) != hipSuccess)
+        return;
+    (void)hipEventRecord(a, s);
+    g_cur_a = a;
+    g_cur_name = name;
+}
+
+void prof_end(hipStream_t s)
+{
+    if (!g_prof_on || !g_cur_a)
+        return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess)
+        return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_pending.push_back({g_cur_name, g_cur_a, b});
+    g_cur_a = nullptr;
+}
+
+hipError_t launch_backward(const float* g, const uint32_t* w1, const uint32_t* w2, int64_t n, float eb, float eta,
+                           float power, double* partial, float* out, hipStream_t s);
+
+} // namespace qai
+
+namespace {
+
+constexpr size_t kPartialOffset = 256; // FP64 partial sums of the adjoint reduction
+
+int plain_checked(const float* field, const int64_t dims[3], float eb, const qai_params* params, void* ws,
+                  size_t ws_bytes, float* out, const qai_taps* taps, void* stream, bool keep_w2)
+{
+    int64_t n;
+    int rc = check_dims(dims, &n);
+    if (rc)
+        return rc;
+    if (!field || !out)
+        return fail(QAI_EINVAL, "field and out must be device pointers");
+    if ((rc = check_eb(eb)))
+        return rc;
+    qai_params p;
+    if ((rc = check_params(params, &p)))
+        return rc;
+    const size_t need = qai_workspace_bytes(dims);
+    if (!ws || ws_bytes < need)
+        return fail(QAI_ENOWS, "workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+    if (((uintptr_t)ws & 255u) != 0)
+        return fail(QAI_ENOWS, "workspace must be 256-byte aligned");
+    const float* fe = field + n;
+    if (out != field && ((out > field && out < fe) || (field > out && field < out + n)))
+        return fail(QAI_EINVAL, "out partly overlaps field");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(QAI_ENODEV, "no usable GPU: %s", hipGetErrorString(e));
+
+    qai::Plan1 pl = {};
+    pl.xq = field;
+    pl.out = out;
+    pl.nz = dims[0];
+    pl.ny = dims[1];
+    pl.nx = dims[2];
+    pl.eb = eb;
+    pl.eta = p.eta;
+    pl.power = p.power;
+    unsigned char* w = (unsigned char*)ws;
+    pl.status = (uint32_t*)w;
+    pl.w1 = (uint32_t*)(w + kHeader);
+    pl.w2 = (uint32_t*)(w + kHeader + align256((size_t)n * 4));
+    pl.keep_w2 = keep_w2;
+    if (taps)
+        pl.taps = *taps;
+    qai::Tuning t;
+    qai::default_tuning(t);
+    e = qai::run_plain(pl, t, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail_hip(e, "kernel launch");
+    return QAI_OK;
+}
+
+__global__ void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n16)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_copy_tail(const uint32_t* src, uint32_t* dst, size_t from, size_t n)
+{
+    size_t i = from + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        dst[i] = src[i];
+}
+
+} // namespace
+
+extern "C" {
+
+size_t qai_workspace_bytes(const int64_t dims[3])
+{
+    int64_t n;
+    if (!dims)
+        return 0;
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || dims[a] > QAI_MAX_EXTENT)
+            return 0;
+    n = dims[0] * dims[1] * dims[2];
+    return kHeader + 2 * align256((size_t)n * 4);
+}
+
+int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const qai_params* params, void* ws,
+                    size_t ws_bytes, float* out, const qai_taps* taps, void* stream)
+{
+    g_err.clear();
+    return plain_checked(field, dims, eb, params, ws, ws_bytes, out, taps, stream,
+                         params && (params->flags & QAI_FLAG_KEEP_D2));
+}
+
+int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out, void* stream)
+{
+    g_err.clear();
+    int64_t n;
+    int rc = check_dims(dims, &n);
+    if (rc)
+        return rc;
+    if (!field || !out)
+        return fail(QAI_EINVAL, "field and out must be device pointers");
+    if ((rc = check_eb(eb)))
+        return rc;
+    const size_t need = qai_workspace_bytes(dims);
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, need, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipMallocAsync");
+    rc = plain_checked(field, dims, eb, nullptr, ws, need, out, nullptr, stream, false);
+    e = hipFreeAsync(ws, (hipStream_t)stream);
+    if (rc == QAI_OK && e != hipSuccess)
+        return fail_hip(e, "hipFreeAsync");
+    return rc;
+}
+
+int qai_device_status(const void* ws, void* stream, uint32_t* flags)
+{
+    g_err.clear();
+    if (!ws || !flags)
+        return fail(QAI_EINVAL, "ws and flags must not be NULL");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipStreamSynchronize");
+    e = hipMemcpy(flags, ws, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipMemcpy");
+    return QAI_OK;
+}
+
+const char* qai_last_error(void) { return g_err.c_str(); }
+
+int qai_backward(const float* grad_out, void* ws_saved, size_t ws_bytes, const int64_t dims[3], float eb,
+                 const qai_params* params, float* grad_params, void* stream)
+{
+    g_err.clear();
+    int64_t n;
+    int rc = check_dims(dims, &n);
+    if (rc)
+        return rc;
+    if (!grad_out || !grad_params)
+        return fail(QAI_EINVAL, "grad_out and grad_params must be device pointers");
+    if ((rc = check_eb(eb)))
+        return rc;
+    qai_params p;
+    if ((rc = check_params(params, &p)))
+        return rc;
+    const size_t need = qai_workspace_bytes(dims);
+    if (!ws_saved || ws_bytes < need)
+        return fail(QAI_ENOWS, "workspace of %zu bytes needed, %zu given", need, ws_saved ? ws_bytes : (size_t)0);
+    unsigned char* w = (unsigned char*)ws_saved;
+    const uint32_t* w1 = (const uint32_t*)(w + kHeader);
+    const uint32_t* w2 = (const uint32_t*)(w + kHeader + align256((size_t)n * 4));
+    hipError_t e = qai::launch_backward(grad_out, w1, w2, n, eb, p.eta, p.power, (double*)(w + kPartialOffset),
+                                        grad_params, (hipStream_t)stream);
+    return e == hipSuccess ? QAI_OK : fail_hip(e, "backward launch");
+}
+
+int qai_copy_probe(const void* src, void* dst, size_t n_words, void* stream)
+{
+    g_err.clear();
+    if (!src || !dst)
+        return fail(QAI_EINVAL, "src and dst must not be NULL");
+    if (n_words == 0)
+        return QAI_OK;
+    const size_t n16 = ((((uintptr_t)src | (uintptr_t)dst) & 15u) == 0) ? n_words / 4 : 0;
+    if (n16) {
+        size_t blocks = (n16 + 255) / 256;
+        if (blocks > 8192)
+            blocks = 8192;
+        hipLaunchKernelGGL(k_copy, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, (const uint4*)src,
+                           (uint4*)dst, n16);
+    }
+    const size_t from = n16 * 4;
+    if (from < n_words) {
+        const size_t rest = n_words - from;
+        hipLaunchKernelGGL(k_copy_tail, dim3((uint32_t)((rest + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint32_t*)src, (uint32_t*)dst, from, n_words);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? QAI_OK : fail_hip(e, "copy launch");
+}
+
+int qai_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return QAI_OK;
+}
+
+int qai_stage_times(double* ms, const char** names, int n, int* n_stages, int reset)
+{
+    g_err.clear();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& r : g_pending) {
+        hipError_t e = hipEventSynchronize(r.b);
+        float t = 0.0f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&t, r.a, r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+        if (e != hipSuccess)
+            continue;
+        bool found = false;
+        for (auto& kv : g_acc)
+            if (strcmp(kv.first, r.name) == 0) {
+                kv.second += t;
+                found = true;
+                break;
+            }
+        if (!found)
+            g_acc.push_back({r.name, (double)t});
+    }
+    g_pending.clear();
+    const int k = (int)g_acc.size();
+    if (n_stages)
+        *n_stages = k;
+    for (int i = 0; i < k && i < n; ++i) {
+        if (ms)
+            ms[i] = g_acc[i].second;
+        if (names)
+            names[i] = g_acc[i].first;
+    }
+    if (reset)
+        g_acc.clear();
+    return QAI_OK;
+}
+
+} // extern "C"

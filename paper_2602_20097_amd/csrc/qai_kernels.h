@@ -1,0 +1,93 @@
+// qai_kernels.h -- kernel argument blocks and the host-side launchers of the
+// plain post-pass (used by the C ABI, the batched plan and the autotuner).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qai.h"
+
+namespace qai {
+
+// Stage A (+ the first EDT pass) or stage C (+ the first pass of the second
+// EDT): a 6-neighbour stencil marks the sites, then a scan along x gives each
+// voxel its nearest site on its x-line.
+struct SeedArgs {
+    const float* xq;      // mode 0 input: decompressed field
+    const uint32_t* w1;   // mode 1 input: final words of the first EDT
+    uint32_t* wout;       // output words
+    int64_t nx, ny, nz;
+    float inv2eb, two_eb; // 1/(2 eb) rounded, 2 eb exact
+    uint32_t* status;
+    int32_t* tq;          // taps (nullable)
+    uint8_t* tb1;
+    int8_t* tsb;
+    int8_t* ts;
+    int32_t* td1;
+    uint8_t* tb2;
+    uint64_t ngroups;     // line groups (one line per wave)
+    int waves;            // waves per workgroup
+};
+
+// One lower-envelope pass along y (axis 1) or z (axis 2) over packed words,
+// optionally finished by the interpolation of step E.
+struct EnvArgs {
+    uint32_t* w;
+    int64_t nx, ny, nz;
+    int tx_log2;          // columns per tile = 1 << tx_log2
+    uint64_t ntiles;
+    bool write_words;     // store the pass result (always, except an epilogue pass that need not)
+    // epilogue
+    const uint32_t* w1;
+    const float* xq;
+    float* out;
+    float eta_eb, power;
+    int32_t* td2;
+    float* tw;
+};
+
+struct InterpArgs {
+    const uint32_t* w1;
+    const uint32_t* w2;
+    const float* xq;
+    float* out;
+    int64_t n;
+    float eta_eb, power;
+    int32_t* td2;
+    float* tw;
+};
+
+// Launch geometry chosen per pass (the autotuner overrides the defaults).
+struct Tuning {
+    int env_tx_log2[3];   // per axis (index 1 = y, 2 = z); -1 = default
+    int env_threads;      // threads per envelope workgroup
+};
+
+void default_tuning(Tuning& t);
+
+// Host launchers: return hipSuccess or the launch error.
+hipError_t launch_seed(int mode, const SeedArgs& a, hipStream_t s);
+hipError_t launch_env(int axis, bool epilogue, EnvArgs a, const Tuning& t, hipStream_t s);
+hipError_t launch_interp(const InterpArgs& a, hipStream_t s);
+hipError_t launch_clear(uint32_t* p, int n, hipStream_t s);
+
+// The full plain post-pass on one field (stages in order).  ws_words points
+// at 2*N words (w1 then w2), status at one word.
+struct Plan1 {
+    const float* xq;
+    float* out;
+    int64_t nz, ny, nx;
+    float eb, eta, power;
+    uint32_t* w1;
+    uint32_t* w2;
+    uint32_t* status;
+    bool keep_w2;
+    qai_taps taps;
+};
+hipError_t run_plain(const Plan1& p, const Tuning& t, hipStream_t s);
+
+// Stage-timing hooks (active when profiling is enabled).
+void prof_begin(const char* name, hipStream_t s);
+void prof_end(hipStream_t s);
+
+} // namespace qai

@@ -1,0 +1,86 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+include/qai.h declares, sizes workspaces, and rejects bad arguments on the
+host before anything is enqueued."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2602_20097_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qai.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qai_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "qai_mitigate" in names and "qai_mitigate_ex" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_workspace_bytes(lib):
+    for shape in ((1, 1, 1), (64, 64, 64), (256, 384, 384), (1, 1800, 3600)):
+        n = math.prod(shape)
+        b = lib.qai_workspace_bytes(_lib.Dims(*shape))
+        words = 2 * (((n * 4) + 255) // 256) * 256
+        assert b == 64 * 1024 + words
+    for bad in ((0, 4, 4), (4, -1, 4), (1, 1, 16385)):
+        assert lib.qai_workspace_bytes(_lib.Dims(*bad)) == 0
+    assert lib.qai_workspace_bytes(None) == 0
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+def call_ex(lib, field=FAKE, dims=(4, 4, 4), eb=0.1, params=None, ws=FAKE, ws_bytes=1 << 30, out=FAKE):
+    prm = ctypes.byref(params) if params is not None else None
+    d = _lib.Dims(*dims) if dims is not None else None
+    return lib.qai_mitigate_ex(field, d, ctypes.c_float(eb), prm, ws, ws_bytes, out, None, None)
+
+
+def test_argument_errors_are_caught_on_the_host(lib):
+    assert call_ex(lib, dims=(0, 4, 4)) == -2
+    assert call_ex(lib, dims=(4, 4, 20000)) == -2
+    assert call_ex(lib, dims=None) == -1
+    assert call_ex(lib, field=None) == -1
+    assert call_ex(lib, out=None) == -1
+    for eb in (0.0, -1.0, float("nan"), float("inf"), 1e-45):
+        assert call_ex(lib, eb=eb) == -1, eb
+    assert call_ex(lib, params=_lib.Params(float("nan"), 1.0, 0)) == -1
+    assert call_ex(lib, params=_lib.Params(0.9, 0.0, 0)) == -1
+    assert call_ex(lib, ws=None) == -3
+    assert call_ex(lib, ws_bytes=100) == -3
+    assert call_ex(lib, ws=ctypes.c_void_p(0x1010)) == -3  # misaligned
+    # out overlapping field partly
+    assert call_ex(lib, field=ctypes.c_void_p(0x100000), out=ctypes.c_void_p(0x100004)) == -1
+    msg = lib.qai_last_error().decode()
+    assert "overlap" in msg
+    assert lib.qai_mitigate(FAKE, _lib.Dims(4, 0, 4), ctypes.c_float(0.1), FAKE, None) == -2
+    assert lib.qai_backward(None, FAKE, 1 << 30, _lib.Dims(4, 4, 4), ctypes.c_float(0.1), None, FAKE, None) == -1
+    assert lib.qai_copy_probe(None, FAKE, 4, None) == -1
+
+
+def test_no_device_is_reported_without_a_launch(lib):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present; this checks the no-device path")
+    except Exception:
+        pass
+    assert call_ex(lib) == -5
+    assert "GPU" in lib.qai_last_error().decode()

@@ -1,0 +1,156 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bit-exact for the indices, masks, signs and squared distances; the
+compensated output within 1e-6 * max(|out_oracle|, eb), the FP32-vs-FP64
+tolerance derived in the design notes (FP32 relative error of C is a few
+ulp of |C| <= 0.9 eb, plus half an ulp of |out| from the final add)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_20097_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-6
+KEYS = ("q", "b1", "sb", "s", "d1sq", "b2", "d2sq")
+
+
+def gpu_run(xq, eb, eta=0.9, power=1.0):
+    import paper_2602_20097_amd as qai
+    t = torch.from_numpy(np.ascontiguousarray(xq, np.float32)).cuda()
+    out, taps = qai.mitigate(t, eb, eta, power, taps=True)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in taps.items()}
+    res["out"] = out.cpu().numpy()
+    return res
+
+
+def assert_parity(xq, eb, eta=0.9, power=1.0, label=""):
+    print(f"parity case {label} shape={xq.shape} eb={eb:.6g}", flush=True)
+    g = gpu_run(xq, eb, eta, power)
+    r = oracle.qai(xq, eb, eta, power)
+    for k in KEYS:
+        a, b = g[k], r[k]
+        if not np.array_equal(a.astype(np.int64), b.astype(np.int64)):
+            bad = np.argwhere(a.astype(np.int64) != b.astype(np.int64))
+            raise AssertionError(f"{label}: tap {k} differs at {len(bad)} voxels, first {bad[:5].tolist()}: "
+                                 f"gpu {a[tuple(bad[0])]} oracle {b[tuple(bad[0])]}")
+    err = np.abs(g["out"].astype(np.float64) - r["out"])
+    lim = REL_TOL * np.maximum(np.abs(r["out"]), eb)
+    assert (err <= lim).all(), f"{label}: out off by {err.max():.3g} (limit {lim[np.argmax(err - lim)]:.3g})"
+    np.testing.assert_allclose(g["w"], r["w"], rtol=0, atol=1e-6)
+    return g, r
+
+
+def test_w1_grf64():
+    x32, xq, q, eb = synth.make_workload("grf64_k3_eb1e-2")
+    g, _ = assert_parity(xq, eb, label="grf64")
+    assert np.array_equal(g["q"], q)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_tiny_grids(seed):
+    rng = np.random.default_rng(1000 + seed)
+    for it in range(30):
+        shape = tuple(int(v) for v in rng.integers(1, 9, size=3))
+        levels = int(rng.integers(1, 5))
+        q = rng.integers(-levels, levels + 1, size=shape)
+        xq = (q * 1.0).astype(np.float32)
+        assert_parity(xq, 0.5, label=f"tiny{seed}.{it}")
+
+
+def test_hand_examples():
+    k = np.arange(32)
+    for q in (k // 8, (np.arange(15) // 5), np.array([0, 0, 0, 1, 2, 2, 2]), np.array([2, 2, 2, 1, 0, 0, 0])):
+        assert_parity(q.astype(np.float32)[None, None, :], 0.5, label="1d")
+        assert_parity(q.astype(np.float32)[None, :, None], 0.5, label="1d-y")
+        assert_parity(q.astype(np.float32)[:, None, None], 0.5, label="1d-z")
+    q = np.zeros((1, 3, 3))
+    q[0, 1, 2] = 1
+    q[0, 2, 1] = -1
+    assert_parity(q.astype(np.float32), 0.5, label="corner")
+    assert_parity(np.broadcast_to(k // 8, (3, 3, 32)).astype(np.float32).copy(), 0.5, label="extrusion")
+
+
+SHAPES = [(5, 70, 130), (3, 65, 200), (1, 1, 1000), (1, 300, 1), (17, 1, 129), (9, 33, 1), (2, 2, 2),
+          (1, 1, 1), (4, 129, 63), (70, 5, 66), (1, 257, 300), (33, 33, 33)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_ragged_shapes_smooth_fields(shape):
+    for rel in (2e-2, 2e-3):
+        x = synth.grf(shape, 3.0, 77 + sum(shape))
+        if np.ptp(x) == 0:  # a single voxel has no range: any bound will do
+            x = np.zeros(shape)
+            xq, eb = x.astype(np.float32), 0.5
+        else:
+            x32, xq, q, eb = synth.quantize(x, rel)
+        assert_parity(xq, eb, label=f"ragged{shape}")
+
+
+def test_adversarial_fields():
+    n = (20, 24, 28)
+    assert_parity(np.full(n, 3.0, np.float32), 0.5, label="constant")
+    q = np.zeros(n)
+    q[10, 12, 14] = 1
+    assert_parity(q.astype(np.float32), 0.5, label="single-bump")
+    cz, cy, cx = np.meshgrid(*[np.arange(s) for s in n], indexing="ij")
+    assert_parity(((cz + cy + cx) % 2).astype(np.float32), 0.5, label="checkerboard")
+    assert_parity(((cx // 3) % 2).astype(np.float32), 0.5, label="stripes")
+    assert_parity((cx // 5 + cy // 7).astype(np.float32), 0.5, label="terraces")
+    assert_parity(np.where(cx < 14, 0, 1).astype(np.float32), 0.5, label="one-step")
+    big = np.zeros((3, 4, 700))
+    big[1, 1, 350] = 2
+    assert_parity(big.astype(np.float32), 0.5, label="far-single")
+    # long lines and few sites: exercises long searches and absent sites
+    q = np.zeros((3, 1500, 3))
+    q[1, 100, 1] = 1
+    assert_parity(q.astype(np.float32), 0.5, label="long-y")
+
+
+def test_parameters_eta_power():
+    x32, xq, q, eb = synth.make_workload("grf64_k3_eb1e-2")
+    for eta, p in ((0.5, 1.0), (1.0, 2.0), (0.9, 0.5)):
+        assert_parity(xq, eb, eta, p, label=f"eta{eta}p{p}")
+
+
+def test_determinism_and_in_place():
+    import paper_2602_20097_amd as qai
+    x32, xq, q, eb = synth.make_workload("grf64_k3_eb1e-2")
+    t = torch.from_numpy(xq).cuda()
+    a = qai.mitigate(t, eb)
+    b = qai.mitigate(t, eb)
+    c = qai.mitigate_simple(t, eb)
+    u = t.clone()
+    qai.mitigate(u, eb, out=u)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(a, u)
+
+
+def test_status_flag_for_out_of_range_indices():
+    import paper_2602_20097_amd as qai
+    xq = np.zeros((4, 5, 6), np.float32)
+    xq[2, 2, 2] = 1e9
+    t = torch.from_numpy(xq).cuda()
+    ws = qai.new_workspace(t.shape)
+    qai.mitigate(t, 0.5, workspace=ws)
+    assert qai.device_status(ws) & qai.QAI_STATUS_QRANGE
+    qai.mitigate(torch.zeros_like(t), 0.5, workspace=ws)
+    assert qai.device_status(ws) == 0
+
+
+@pytest.mark.parametrize("name", ["modes256x384x384_eb1e-2", "modes256x384x384_eb1e-3",
+                                  "modes256x384x384_eb1e-4", "grf2d_1800x3600_k11/3_eb1e-3"])
+def test_full_size_workloads(name):
+    x32, xq, q, eb = synth.make_workload(name)
+    g, r = assert_parity(xq, eb, label=name)
+    assert np.array_equal(g["q"], q)
+
+
+def test_headline_512_full_parity():
+    x32, xq, q, eb = synth.make_workload("grf512_k11/3_eb1e-3")
+    g, r = assert_parity(xq, eb, label="grf512")
+    # the relaxed bound of Section VII-C on the whole field
+    assert np.abs(g["out"].astype(np.float64) - x32).max() <= (1 + 0.9) * eb * (1 + 1e-6)
