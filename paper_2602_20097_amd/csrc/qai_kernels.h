@@ -60,7 +60,8 @@ struct InterpArgs {
 // Launch geometry chosen per pass (the autotuner overrides the defaults).
 struct Tuning {
     int env_tx_log2[3];   // per axis (index 1 = y, 2 = z); -1 = default
-    int env_threads;      // threads per envelope workgroup
+    int env_algo[3];      // per axis: 0 = banded envelope, 1 = windowed search
+    int env_threads;      // threads per workgroup of the windowed variant
 };
 
 void default_tuning(Tuning& t);
