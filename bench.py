@@ -30,16 +30,15 @@ METRIC = "QAI post-pass GB/s of FP32 field and % HBM roofline, plain vs batched,
 HBM_PEAK_GBPS = 8000.0
 
 # Algorithmic HBM bytes per voxel of each stage (reads + writes of the
-# arrays the stage must touch once): the post-pass moves 56 B/voxel in 3-D.
+# arrays the stage must touch once): the post-pass moves 64 B/voxel in 3-D.
 STAGE_BYTES = {
     "seed1_xscan": 8,     # read x', write first-EDT words
     "edt1_y": 8,          # read + write words
     "edt1_z": 8,
     "seed2_xscan": 8,     # read first-EDT words, write second-EDT words
     "edt2_y": 8,
-    "edt2_z_interp": 16,  # read second-EDT words, first-EDT words, x'; write out
-    "edt2_y_interp": 16,
-    "interp": 16,
+    "edt2_z": 8,
+    "interp": 16,         # read second-EDT words, first-EDT words, x'; write out
     "clear": 0,
 }
 

@@ -49,15 +49,12 @@ enum {
 /* Interpolation parameters (Section V, step E).  eta is the boundary
  * magnitude factor (the paper uses 0.9); power is the inverse-distance
  * exponent p of w = k1^-p / (k1^-p + k2^-p) (the paper's weight is p = 1).
- * flags: QAI_FLAG_KEEP_D2 keeps the second EDT's words in the workspace
- * (4 more bytes written per voxel), which qai_backward needs. */
+ * flags is reserved and must be 0. */
 typedef struct {
     float eta;
     float power;
     uint32_t flags;
 } qai_params;
-
-#define QAI_FLAG_KEEP_D2 0x1u
 
 /* Optional per-voxel intermediates, each a device array of N = nz*ny*nx
  * entries or NULL:
@@ -94,17 +91,17 @@ typedef struct {
  * that must not allocate use qai_mitigate_ex. */
 int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out, void* stream);
 
-/* Bytes of device workspace qai_mitigate_ex needs for dims: two 32-bit words
- * per voxel plus a 64 KiB header (status word, reduction partials).  0 for
- * invalid dims. */
+/* Bytes of device workspace qai_mitigate_ex needs for dims: three 32-bit
+ * words per voxel (the packed distance words of the passes, ping-ponged) plus
+ * a 64 KiB header (status word, reduction partials).  0 for invalid dims. */
 size_t qai_workspace_bytes(const int64_t dims[3]);
 
 /* qai_mitigate_ex -- as qai_mitigate with explicit parameters (NULL = the
  * defaults), a caller-owned device workspace ws of ws_bytes >=
  * qai_workspace_bytes(dims) (any alignment of 256 bytes or more), and optional
- * taps (NULL = none).  With QAI_FLAG_KEEP_D2 the workspace afterwards holds
- * the two distance words per voxel that qai_backward consumes; keep it
- * untouched until then. */
+ * taps (NULL = none).  Afterwards the workspace holds the final distance
+ * words of both EDTs, which qai_backward consumes; keep it untouched until
+ * then. */
 int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const qai_params* params,
                     void* ws, size_t ws_bytes, float* out, const qai_taps* taps, void* stream);
 
@@ -115,9 +112,9 @@ int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const q
  *   dL/d power = sum_i g_i * S_i * eta * eb * (-w_i (1 - w_i) ln(k1_i / k2_i))
  * (0 wherever w is pinned at 0 or 1).
  *   grad_out     device FP32[N], dL/d out
- *   ws_saved     the workspace of the qai_mitigate_ex call (made with
- *                QAI_FLAG_KEEP_D2) being differentiated; its header is reused
- *                for the partial sums
+ *   ws_saved     the workspace of the qai_mitigate_ex call being
+ *                differentiated (same dims); its header is reused for the
+ *                partial sums
  *   grad_params  device FP32[2] receiving {dL/d eta, dL/d power} (overwritten)
  * The reduction is deterministic (fixed tree, FP64 partial sums). */
 int qai_backward(const float* grad_out, void* ws_saved, size_t ws_bytes, const int64_t dims[3],

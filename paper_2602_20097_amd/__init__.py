@@ -60,16 +60,15 @@ _TAP_TYPES = dict(q=torch.int32, b1=torch.uint8, sb=torch.int8, s=torch.int8, d1
                   b2=torch.uint8, d2sq=torch.int32, w=torch.float32)
 
 
-def mitigate(field, eb, eta=0.9, power=1.0, *, taps=False, out=None, workspace=None, keep_d2=False,
-             stream=None):
+def mitigate(field, eb, eta=0.9, power=1.0, *, taps=False, out=None, workspace=None, stream=None):
     """Run the QAI post-pass on a decompressed float32 CUDA tensor.
 
     ``eb`` is the absolute error bound of the pre-quantization (Eq. 1).
     Returns ``out`` or, with ``taps=True``, ``(out, dict_of_intermediates)``
     (``q``, ``b1``, ``sb``, ``s``, ``d1sq``, ``b2``, ``d2sq``, ``w``).
     ``workspace`` (optional) is a uint8 device tensor of at least
-    ``workspace_bytes(field.shape)`` bytes; ``keep_d2`` keeps the distances
-    the adjoint needs in it.
+    ``workspace_bytes(field.shape)`` bytes; afterwards it holds the distance
+    words the adjoint (``backward``) needs.
     """
     L = lib()
     dims = _check_field(field)
@@ -86,7 +85,7 @@ def mitigate(field, eb, eta=0.9, power=1.0, *, taps=False, out=None, workspace=N
     if taps:
         tap_t = {k: torch.empty(field.shape, dtype=v, device=field.device) for k, v in _TAP_TYPES.items()}
         tp = _lib.Taps(**{k: v.data_ptr() for k, v in tap_t.items()})
-    prm = _lib.Params(float(eta), float(power), _lib.QAI_FLAG_KEEP_D2 if keep_d2 else 0)
+    prm = _lib.Params(float(eta), float(power), 0)
     rc = L.qai_mitigate_ex(ctypes.c_void_p(field.data_ptr()), dims, ctypes.c_float(eb), ctypes.byref(prm),
                            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                            ctypes.c_void_p(out.data_ptr()), ctypes.byref(tp) if tp is not None else None,
@@ -115,7 +114,7 @@ def device_status(workspace, stream=None):
 
 def backward(grad_out, workspace, shape, eb, eta=0.9, power=1.0, stream=None):
     """Adjoint of step E: returns a float32 CUDA tensor ``[dL/deta, dL/dpower]``
-    for a workspace filled by ``mitigate(..., keep_d2=True)``."""
+    for a workspace filled by ``mitigate(..., workspace=ws)`` on the same shape."""
     L = lib()
     _check_field(grad_out, "grad_out")
     g = torch.empty(2, dtype=torch.float32, device=grad_out.device)
@@ -136,7 +135,7 @@ class QAIFunction(torch.autograd.Function):
     def forward(ctx, x_dec, eta, power, eb):
         ws = new_workspace(x_dec.shape, x_dec.device)
         e, p = float(eta), float(power)
-        out = mitigate(x_dec.detach().contiguous(), eb, e, p, workspace=ws, keep_d2=True)
+        out = mitigate(x_dec.detach().contiguous(), eb, e, p, workspace=ws)
         ctx.save_for_backward(ws)
         ctx.meta = (tuple(x_dec.shape), float(eb), e, p, eta.dtype, power.dtype)
         return out

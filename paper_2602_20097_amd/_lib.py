@@ -17,7 +17,6 @@ LIB_PATH = os.path.join(PKG, "libqai.so")
 QAI_OK = 0
 ERRORS = {-1: "QAI_EINVAL", -2: "QAI_EDIMS", -3: "QAI_ENOWS", -4: "QAI_EHIP", -5: "QAI_ENODEV",
           -6: "QAI_ESTATE"}
-QAI_FLAG_KEEP_D2 = 0x1
 QAI_STATUS_QRANGE = 0x1
 MAX_EXTENT = 16384
 

@@ -68,6 +68,8 @@ int check_params(const qai_params* p, qai_params* out)
         return fail(QAI_EINVAL, "eta must be finite");
     if (!isfinite(d.power) || !(d.power > 0.0f))
         return fail(QAI_EINVAL, "power must be finite and > 0");
+    if (d.flags != 0u)
+        return fail(QAI_EINVAL, "params.flags is reserved and must be 0");
     *out = d;
     return QAI_OK;
 }
@@ -115,6 +117,7 @@ void prof_end(hipStream_t s)
 
 hipError_t launch_backward(const float* g, const uint32_t* w1, const uint32_t* w2, int64_t n, float eb, float eta,
                            float power, double* partial, float* out, hipStream_t s);
+void final_buffers(int64_t nz, int64_t ny, int64_t nx, int& w1, int& w2);
 
 } // namespace qai
 
@@ -122,8 +125,13 @@ namespace {
 
 constexpr size_t kPartialOffset = 256; // FP64 partial sums of the adjoint reduction
 
+uint32_t* word_buffer(void* ws, int64_t n, int k)
+{
+    return (uint32_t*)((unsigned char*)ws + kHeader + (size_t)k * align256((size_t)n * 4));
+}
+
 int plain_checked(const float* field, const int64_t dims[3], float eb, const qai_params* params, void* ws,
-                  size_t ws_bytes, float* out, const qai_taps* taps, void* stream, bool keep_w2)
+                  size_t ws_bytes, float* out, const qai_taps* taps, void* stream)
 {
     int64_t n;
     int rc = check_dims(dims, &n);
@@ -158,11 +166,10 @@ int plain_checked(const float* field, const int64_t dims[3], float eb, const qai
     pl.eb = eb;
     pl.eta = p.eta;
     pl.power = p.power;
-    unsigned char* w = (unsigned char*)ws;
-    pl.status = (uint32_t*)w;
-    pl.w1 = (uint32_t*)(w + kHeader);
-    pl.w2 = (uint32_t*)(w + kHeader + align256((size_t)n * 4));
-    pl.keep_w2 = keep_w2;
+    pl.status = (uint32_t*)ws;
+    pl.bufA = word_buffer(ws, n, 0);
+    pl.bufB = word_buffer(ws, n, 1);
+    pl.bufC = word_buffer(ws, n, 2);
     if (taps)
         pl.taps = *taps;
     qai::Tuning t;
@@ -199,15 +206,14 @@ size_t qai_workspace_bytes(const int64_t dims[3])
         if (dims[a] < 1 || dims[a] > QAI_MAX_EXTENT)
             return 0;
     n = dims[0] * dims[1] * dims[2];
-    return kHeader + 2 * align256((size_t)n * 4);
+    return kHeader + 3 * align256((size_t)n * 4);
 }
 
 int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const qai_params* params, void* ws,
                     size_t ws_bytes, float* out, const qai_taps* taps, void* stream)
 {
     g_err.clear();
-    return plain_checked(field, dims, eb, params, ws, ws_bytes, out, taps, stream,
-                         params && (params->flags & QAI_FLAG_KEEP_D2));
+    return plain_checked(field, dims, eb, params, ws, ws_bytes, out, taps, stream);
 }
 
 int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out, void* stream)
@@ -226,7 +232,7 @@ int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out
     hipError_t e = hipMallocAsync(&ws, need, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail_hip(e, "hipMallocAsync");
-    rc = plain_checked(field, dims, eb, nullptr, ws, need, out, nullptr, stream, false);
+    rc = plain_checked(field, dims, eb, nullptr, ws, need, out, nullptr, stream);
     e = hipFreeAsync(ws, (hipStream_t)stream);
     if (rc == QAI_OK && e != hipSuccess)
         return fail_hip(e, "hipFreeAsync");
@@ -267,11 +273,13 @@ int qai_backward(const float* grad_out, void* ws_saved, size_t ws_bytes, const i
     const size_t need = qai_workspace_bytes(dims);
     if (!ws_saved || ws_bytes < need)
         return fail(QAI_ENOWS, "workspace of %zu bytes needed, %zu given", need, ws_saved ? ws_bytes : (size_t)0);
-    unsigned char* w = (unsigned char*)ws_saved;
-    const uint32_t* w1 = (const uint32_t*)(w + kHeader);
-    const uint32_t* w2 = (const uint32_t*)(w + kHeader + align256((size_t)n * 4));
-    hipError_t e = qai::launch_backward(grad_out, w1, w2, n, eb, p.eta, p.power, (double*)(w + kPartialOffset),
-                                        grad_params, (hipStream_t)stream);
+    int k1, k2;
+    qai::final_buffers(dims[0], dims[1], dims[2], k1, k2);
+    const uint32_t* w1 = word_buffer(ws_saved, n, k1);
+    const uint32_t* w2 = word_buffer(ws_saved, n, k2);
+    hipError_t e = qai::launch_backward(grad_out, w1, w2, n, eb, p.eta, p.power,
+                                        (double*)((unsigned char*)ws_saved + kPartialOffset), grad_params,
+                                        (hipStream_t)stream);
     return e == hipSuccess ? QAI_OK : fail_hip(e, "backward launch");
 }
 

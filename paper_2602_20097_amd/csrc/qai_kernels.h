@@ -32,7 +32,8 @@ struct SeedArgs {
 // One lower-envelope pass along y (axis 1) or z (axis 2) over packed words,
 // optionally finished by the interpolation of step E.
 struct EnvArgs {
-    uint32_t* w;
+    const uint32_t* win;  // words before the pass
+    uint32_t* w;          // words after the pass (may equal win for the tiled variants)
     int64_t nx, ny, nz;
     int tx_log2;          // columns per tile = 1 << tx_log2
     uint64_t ntiles;
@@ -60,32 +61,40 @@ struct InterpArgs {
 // Launch geometry chosen per pass (the autotuner overrides the defaults).
 struct Tuning {
     int env_tx_log2[3];   // per axis (index 1 = y, 2 = z); -1 = default
-    int env_algo[3];      // per axis: 0 = banded envelope, 1 = windowed search
+    int env_algo[3];      // per axis: 0 = streaming envelope, 1 = windowed search, 2 = banded
+    int stream_cap[3];    // per axis: live-stack ring entries of the streaming envelope, second EDT
+    int edt1_cap[3];      // the same for the first EDT (16, 32 or 64)
+    int edt1_algo[3];     // env_algo for the first EDT
     int env_threads;      // threads per workgroup of the windowed variant
+    int seed_ty, seed_tz; // x-lines (waves) and z-planes per workgroup of the seed passes
 };
 
 void default_tuning(Tuning& t);
 
 // Host launchers: return hipSuccess or the launch error.
-hipError_t launch_seed(int mode, const SeedArgs& a, hipStream_t s);
+hipError_t launch_seed(int mode, const SeedArgs& a, hipStream_t s, int ty, int tz);
 hipError_t launch_env(int axis, bool epilogue, EnvArgs a, const Tuning& t, hipStream_t s);
 hipError_t launch_interp(const InterpArgs& a, hipStream_t s);
 hipError_t launch_clear(uint32_t* p, int n, hipStream_t s);
 
 // The full plain post-pass on one field (stages in order).  ws_words points
 // at 2*N words (w1 then w2), status at one word.
+// Word buffers rotate through the passes: A, B and C hold N words each.  On
+// return w1_final / w2_final point at the final words of the two EDTs.
 struct Plan1 {
     const float* xq;
     float* out;
     int64_t nz, ny, nx;
     float eb, eta, power;
-    uint32_t* w1;
-    uint32_t* w2;
+    uint32_t* bufA;
+    uint32_t* bufB;
+    uint32_t* bufC;
     uint32_t* status;
-    bool keep_w2;
     qai_taps taps;
+    const uint32_t* w1_final;
+    const uint32_t* w2_final;
 };
-hipError_t run_plain(const Plan1& p, const Tuning& t, hipStream_t s);
+hipError_t run_plain(Plan1& p, const Tuning& t, hipStream_t s);
 
 // Stage-timing hooks (active when profiling is enabled).
 void prof_begin(const char* name, hipStream_t s);

@@ -19,14 +19,26 @@
 namespace qai {
 
 // ------------------------------------------------------------------ seeds
-// One wave per x-line.  Forward sweep over 64-voxel chunks: stencil, site
-// flags by ballot, per-chunk masks and the last site before each chunk kept
-// in LDS.  Backward sweep: nearest site to the left (highest set bit at or
-// below the lane, else the carried one) and to the right; the left one wins
-// ties (lower x, as Algorithm 1's strict query comparison).
+// One wave per x-line.  The line is visited in groups of 8 chunks of 64
+// voxels; all stencil loads of a group are issued together.  Forward over
+// the chunks: stencil, site flags by ballot, per-chunk masks, site codes and
+// the last site before each chunk kept in LDS.  Backward: the nearest site to
+// the left (highest set bit at or below the lane, else the carried one) and
+// to the right; the left one wins ties (lower x, as Algorithm 1's strict
+// query comparison).  Lanes past the end of the line read a valid word and
+// ignore it.
+template <int MODE>
+__device__ __forceinline__ int seed_key(const SeedArgs& a, int64_t i, bool& bad)
+{
+    if (MODE == 0)
+        return recover_q(a.xq[i], a.inv2eb, a.two_eb, bad);
+    return word_sign(a.w1[i]);
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_seed_xscan(SeedArgs a)
 {
+    constexpr int CG = 8; // chunks per load group
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t nx = a.nx, ny = a.ny, nz = a.nz;
@@ -38,6 +50,7 @@ __global__ __launch_bounds__(256) void k_seed_xscan(SeedArgs a)
     int* carry = (int*)(masks + nch);
     const int64_t lines = ny * nz;
     const int64_t plane = nx * ny;
+    const bool hy = ny > 1, hz = nz > 1, hx = nx > 1;
 
     for (uint64_t t = blockIdx.x; t < a.ngroups; t += gridDim.x) {
         const uint64_t grp = xcd_remap(t, a.ngroups);
@@ -46,104 +59,101 @@ __global__ __launch_bounds__(256) void k_seed_xscan(SeedArgs a)
             continue;
         const int64_t y = line % ny, z = line / ny;
         const int64_t base = line * nx;
-        const bool line_in = (ny == 1 || (y >= 1 && y <= ny - 2)) && (nz == 1 || (z >= 1 && z <= nz - 2));
+        const bool line_in = (!hy || (y >= 1 && y <= ny - 2)) && (!hz || (z >= 1 && z <= nz - 2));
         bool bad = false;
 
-        int last = -1;   // last site before the current chunk
-        int kprev = 0;   // key at x = 64c - 1
-        for (int c = 0; c < nch; ++c) {
-            const int64_t x = (int64_t)c * 64 + lane;
-            const bool valid = x < nx;
-            int kc = 0;
-            uint32_t wc = QAI_WORD_INF;
-            if (valid) {
+        int last = -1;    // last site before the current chunk
+        int kprev = 0;    // key at x = 64c - 1
+        for (int c0 = 0; c0 < nch; c0 += CG) {
+            int kc[CG], ky0[CG], ky1[CG], kz0[CG], kz1[CG];
+            uint32_t wc[CG];
+#pragma unroll
+            for (int k = 0; k < CG; ++k) {
+                const int64_t x = (int64_t)(c0 + k) * 64 + lane;
+                const int64_t xs = x < nx ? x : nx - 1;   // clamped: always a valid address
                 if (MODE == 0) {
-                    kc = recover_q(a.xq[base + x], a.inv2eb, a.two_eb, bad);
+                    kc[k] = recover_q(a.xq[base + xs], a.inv2eb, a.two_eb, bad);
+                    wc[k] = 0u;
                 } else {
-                    wc = a.w1[base + x];
-                    kc = word_sign(wc);
+                    wc[k] = a.w1[base + xs];
+                    kc[k] = word_sign(wc[k]);
+                }
+                if (line_in) {
+                    ky0[k] = hy ? seed_key<MODE>(a, base + xs - nx, bad) : kc[k];
+                    ky1[k] = hy ? seed_key<MODE>(a, base + xs + nx, bad) : kc[k];
+                    kz0[k] = hz ? seed_key<MODE>(a, base + xs - plane, bad) : kc[k];
+                    kz1[k] = hz ? seed_key<MODE>(a, base + xs + plane, bad) : kc[k];
+                } else {
+                    ky0[k] = ky1[k] = kz0[k] = kz1[k] = kc[k];
                 }
             }
-            int km = __shfl_up(kc, 1);
-            int kp = __shfl_down(kc, 1);
-            if (lane == 0)
-                km = kprev;
-            if (lane == 63 && x + 1 < nx) {
-                if (MODE == 0)
-                    kp = recover_q(a.xq[base + x + 1], a.inv2eb, a.two_eb, bad);
-                else
-                    kp = word_sign(a.w1[base + x + 1]);
-            }
-            kprev = __shfl(kc, 63);
+#pragma unroll
+            for (int k = 0; k < CG; ++k) {
+                const int c = c0 + k;
+                if (c >= nch)
+                    break;
+                const int64_t x = (int64_t)c * 64 + lane;
+                const bool valid = x < nx;
+                int km = __shfl_up(kc[k], 1);
+                int kp = __shfl_down(kc[k], 1);
+                const int knext = (k + 1 < CG) ? __shfl(kc[k + 1 < CG ? k + 1 : k], 0) : 0;
+                if (lane == 0)
+                    km = kprev;
+                if (lane == 63 && x + 1 < nx)
+                    kp = (k + 1 < CG) ? knext : seed_key<MODE>(a, base + x + 1, bad);
+                kprev = __shfl(kc[k], 63);
 
-            const bool x_in = (nx == 1) || (x >= 1 && x <= nx - 2);
-            bool site = false;
-            int sgn = 0;
-            if (valid && line_in && x_in) {
-                if (MODE == 0) {
-                    // Algorithm 2: boundary if some 6-neighbour index differs; sign of the
-                    // first differing neighbour (+x, -x, +y, -y, +z, -z); discarded where an
-                    // absolute central difference reaches 1 (|q+ - q-| >= 2).
-                    int first = 0;
-                    bool steep = false;
-                    if (nx > 1) {
-                        first = (kp != kc) ? kp - kc : ((km != kc) ? km - kc : 0);
-                        steep = abs(kp - km) >= 2;
-                    }
-                    if (ny > 1) {
-                        int a1 = recover_q(a.xq[base + x + nx], a.inv2eb, a.two_eb, bad);
-                        int a0 = recover_q(a.xq[base + x - nx], a.inv2eb, a.two_eb, bad);
-                        if (first == 0)
-                            first = (a1 != kc) ? a1 - kc : ((a0 != kc) ? a0 - kc : 0);
-                        steep = steep || abs(a1 - a0) >= 2;
-                    }
-                    if (nz > 1) {
-                        int a1 = recover_q(a.xq[base + x + plane], a.inv2eb, a.two_eb, bad);
-                        int a0 = recover_q(a.xq[base + x - plane], a.inv2eb, a.two_eb, bad);
-                        if (first == 0)
-                            first = (a1 != kc) ? a1 - kc : ((a0 != kc) ? a0 - kc : 0);
-                        steep = steep || abs(a1 - a0) >= 2;
-                    }
-                    if (first != 0) {
-                        site = true;
-                        sgn = steep ? 0 : (first > 0 ? 1 : -1);
-                    }
-                } else {
-                    // Algorithm 3's GetBoundary(S): interior voxels outside B1 whose
-                    // propagated sign differs from a 6-neighbour's.
-                    const bool on_b1 = (wc != QAI_WORD_INF) && (word_d2(wc) == 0u);
-                    if (!on_b1) {
-                        bool diff = false;
-                        if (nx > 1)
-                            diff = (kp != kc) || (km != kc);
-                        if (ny > 1 && !diff)
-                            diff = (word_sign(a.w1[base + x + nx]) != kc) || (word_sign(a.w1[base + x - nx]) != kc);
-                        if (nz > 1 && !diff)
-                            diff = (word_sign(a.w1[base + x + plane]) != kc) ||
-                                   (word_sign(a.w1[base + x - plane]) != kc);
-                        site = diff;
+                const bool x_in = !hx || (x >= 1 && x <= nx - 2);
+                bool site = false;
+                int sgn = 0;
+                if (valid && line_in && x_in) {
+                    if (MODE == 0) {
+                        // Algorithm 2: boundary if some 6-neighbour index differs; sign of the
+                        // first differing neighbour (+x, -x, +y, -y, +z, -z); discarded where
+                        // an absolute central difference reaches 1 (|q+ - q-| >= 2).
+                        const int q = kc[k];
+                        int first = 0;
+                        if (hx)
+                            first = (kp != q) ? kp - q : ((km != q) ? km - q : 0);
+                        if (hy && first == 0)
+                            first = (ky1[k] != q) ? ky1[k] - q : ((ky0[k] != q) ? ky0[k] - q : 0);
+                        if (hz && first == 0)
+                            first = (kz1[k] != q) ? kz1[k] - q : ((kz0[k] != q) ? kz0[k] - q : 0);
+                        const bool steep = (hx && abs(kp - km) >= 2) || (hy && abs(ky1[k] - ky0[k]) >= 2) ||
+                                           (hz && abs(kz1[k] - kz0[k]) >= 2);
+                        if (first != 0) {
+                            site = true;
+                            sgn = steep ? 0 : (first > 0 ? 1 : -1);
+                        }
+                    } else {
+                        // Algorithm 3's GetBoundary(S): interior voxels outside B1 whose
+                        // propagated sign differs from a 6-neighbour's.
+                        const int sc = kc[k];
+                        const bool on_b1 = (wc[k] != QAI_WORD_INF) && (word_d2(wc[k]) == 0u);
+                        site = !on_b1 && ((hx && (kp != sc || km != sc)) || (hy && (ky0[k] != sc || ky1[k] != sc)) ||
+                                          (hz && (kz0[k] != sc || kz1[k] != sc)));
                     }
                 }
-            }
-            if (MODE == 0)
-                codes[c * 64 + lane] = (unsigned char)sign_code(sgn);
-            const uint64_t m = __ballot(site);
-            if (lane == 0) {
-                masks[c] = m;
-                carry[c] = last;
-            }
-            if (m)
-                last = c * 64 + 63 - __clzll(m);
-            if (valid) {
-                const int64_t i = base + x;
-                if (MODE == 0) {
-                    if (a.tq) a.tq[i] = kc;
-                    if (a.tb1) a.tb1[i] = site ? 1 : 0;
-                    if (a.tsb) a.tsb[i] = (int8_t)(site ? sgn : 0);
-                } else {
-                    if (a.ts) a.ts[i] = (int8_t)kc;
-                    if (a.td1) a.td1[i] = (wc == QAI_WORD_INF) ? -1 : (int32_t)word_d2(wc);
-                    if (a.tb2) a.tb2[i] = site ? 1 : 0;
+                if (MODE == 0)
+                    codes[c * 64 + lane] = (unsigned char)sign_code(sgn);
+                const uint64_t m = __ballot(site);
+                if (lane == 0) {
+                    masks[c] = m;
+                    carry[c] = last;
+                }
+                if (m)
+                    last = c * 64 + 63 - __clzll(m);
+                if (valid) {
+                    const int64_t i = base + x;
+                    if (MODE == 0) {
+                        if (a.tq) a.tq[i] = kc[k];
+                        if (a.tb1) a.tb1[i] = site ? 1 : 0;
+                        if (a.tsb) a.tsb[i] = (int8_t)(site ? sgn : 0);
+                    } else {
+                        if (a.ts) a.ts[i] = (int8_t)kc[k];
+                        if (a.td1) a.td1[i] = (wc[k] == QAI_WORD_INF) ? -1 : (int32_t)word_d2(wc[k]);
+                        if (a.tb2) a.tb2[i] = site ? 1 : 0;
+                    }
                 }
             }
         }
@@ -179,6 +189,183 @@ __global__ __launch_bounds__(256) void k_seed_xscan(SeedArgs a)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// 2.5-D variant of the seed pass.  A workgroup owns Ty adjacent x-lines
+// (one wave each) and marches along z over Tz planes; the stencil keys of
+// rows y-1 .. y+Ty in planes z-1, z, z+1 live in an LDS ring of three planes,
+// so every input word is loaded and converted once per block (plus the halo
+// rows).  Keys: mode 0 the recovered index q; mode 1 the propagated sign S
+// in bits 0-1 and the B1 flag in bit 2.  Each wave then marks its row's sites
+// and runs the same ballot scan along x as k_seed_xscan.
+struct SlabArgs {
+    SeedArgs s;
+    int ty, tz;         // rows (waves) per block, planes per block
+    int rows, planes;   // ring rows (ty + 2, or 1 when ny == 1) and planes (3, or 1 when nz == 1)
+    int64_t nby, nbz;   // blocks along y and z
+};
+
+template <int MODE>
+__device__ __forceinline__ int slab_key(const SeedArgs& a, int64_t i, bool& bad)
+{
+    if (MODE == 0)
+        return recover_q(a.xq[i], a.inv2eb, a.two_eb, bad);
+    const uint32_t w = a.w1[i];
+    const int sgn = word_sign(w);
+    const int b1 = (w != QAI_WORD_INF && word_d2(w) == 0u) ? 4 : 0;
+    return (sgn & 3) | b1;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_seed_slab(SlabArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SeedArgs& a = A.s;
+    const int nx = (int)a.nx;
+    const int64_t ny = a.ny, nz = a.nz;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nch = (nx + 63) >> 6;
+    const size_t ring_bytes = ((size_t)A.planes * A.rows * nx * 4 + 15) & ~(size_t)15;
+    int* ring = (int*)smem;                                       // [plane][row][x]
+    unsigned char* tail = smem + ring_bytes;
+    unsigned char* codes = tail + (size_t)wave * nch * 64;
+    uint64_t* masks = (uint64_t*)(tail + (size_t)A.ty * nch * 64) + (size_t)wave * nch;
+    int* carry = (int*)(tail + (size_t)A.ty * nch * 72) + (size_t)wave * nch;
+    const int64_t plane = (int64_t)nx * ny;
+    const bool hy = ny > 1, hz = nz > 1, hx = nx > 1;
+    const uint64_t nblocks = (uint64_t)(A.nby * A.nbz);
+
+    for (uint64_t t = blockIdx.x; t < nblocks; t += gridDim.x) {
+        const uint64_t bl = xcd_remap(t, nblocks);
+        const int64_t by = (int64_t)(bl % (uint64_t)A.nby), bz = (int64_t)(bl / (uint64_t)A.nby);
+        const int64_t y0 = by * A.ty, z0 = bz * A.tz;
+        const int64_t z1 = min(nz, z0 + A.tz);
+        const int64_t ry0 = hy ? y0 - 1 : y0; // y of ring row 0
+        bool bad = false;
+
+        // stage plane zz into its ring slot (rows outside the domain read as 0)
+        auto stage = [&](int64_t zz) {
+            int* dst = ring + (int)((hz ? (zz + 3) % 3 : 0) * A.rows * nx);
+            for (int r = 0; r < A.rows; ++r) {
+                const int64_t yy = ry0 + r;
+                const bool in = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
+                const int64_t rb = zz * plane + yy * nx;
+                for (int x = threadIdx.x; x < nx; x += blockDim.x)
+                    dst[r * nx + x] = in ? slab_key<MODE>(a, rb + x, bad) : 0;
+            }
+        };
+        __syncthreads();
+        if (hz)
+            stage(z0 - 1);
+        stage(z0);
+        for (int64_t z = z0; z < z1; ++z) {
+            if (hz)
+                stage(z + 1);
+            __syncthreads();
+            const int64_t y = y0 + wave;
+            if (wave < A.ty && y < ny) {
+                const int rc = hy ? wave + 1 : 0;
+                const int* pc = ring + (int)((hz ? z % 3 : 0) * A.rows * nx);
+                const int* pm = hz ? ring + (int)(((z + 2) % 3) * A.rows * nx) : pc;
+                const int* pp = hz ? ring + (int)(((z + 1) % 3) * A.rows * nx) : pc;
+                const int* rowc = pc + rc * nx;
+                const int* rowym = hy ? pc + (rc - 1) * nx : rowc;
+                const int* rowyp = hy ? pc + (rc + 1) * nx : rowc;
+                const int* rowzm = pm + rc * nx;
+                const int* rowzp = pp + rc * nx;
+                const bool line_in = (!hy || (y >= 1 && y <= ny - 2)) && (!hz || (z >= 1 && z <= nz - 2));
+                const int64_t base = (z * ny + y) * nx;
+                int last = -1;
+                for (int c = 0; c < nch; ++c) {
+                    const int x = c * 64 + lane;
+                    const bool valid = x < nx;
+                    const int kc = valid ? rowc[x] : 0;
+                    const bool x_in = !hx || (x >= 1 && x <= nx - 2);
+                    bool site = false;
+                    int sgn = 0;
+                    if (valid && line_in && x_in) {
+                        const int kp = hx ? rowc[x + 1] : kc, km = hx ? rowc[x - 1] : kc;
+                        const int ky1 = rowyp[x], ky0 = rowym[x], kz1 = rowzp[x], kz0 = rowzm[x];
+                        if (MODE == 0) {
+                            // Algorithm 2: boundary if some 6-neighbour index differs; sign of the
+                            // first differing neighbour (+x, -x, +y, -y, +z, -z); discarded where
+                            // an absolute central difference reaches 1 (|q+ - q-| >= 2).
+                            int first = (kp != kc) ? kp - kc : ((km != kc) ? km - kc : 0);
+                            if (first == 0)
+                                first = (ky1 != kc) ? ky1 - kc : ((ky0 != kc) ? ky0 - kc : 0);
+                            if (first == 0)
+                                first = (kz1 != kc) ? kz1 - kc : ((kz0 != kc) ? kz0 - kc : 0);
+                            const bool steep = abs(kp - km) >= 2 || abs(ky1 - ky0) >= 2 || abs(kz1 - kz0) >= 2;
+                            if (first != 0) {
+                                site = true;
+                                sgn = steep ? 0 : (first > 0 ? 1 : -1);
+                            }
+                        } else {
+                            // Algorithm 3's GetBoundary(S): interior voxels outside B1 whose
+                            // propagated sign differs from a 6-neighbour's.
+                            const int sc = kc & 3;
+                            site = !(kc & 4) && (((kp & 3) != sc) || ((km & 3) != sc) || ((ky1 & 3) != sc) ||
+                                                 ((ky0 & 3) != sc) || ((kz1 & 3) != sc) || ((kz0 & 3) != sc));
+                        }
+                    }
+                    if (MODE == 0)
+                        codes[c * 64 + lane] = (unsigned char)sign_code(sgn);
+                    const uint64_t m = __ballot(site);
+                    if (lane == 0) {
+                        masks[c] = m;
+                        carry[c] = last;
+                    }
+                    if (m)
+                        last = c * 64 + 63 - __clzll(m);
+                    if (valid) {
+                        const int64_t i = base + x;
+                        if (MODE == 0) {
+                            if (a.tq) a.tq[i] = kc;
+                            if (a.tb1) a.tb1[i] = site ? 1 : 0;
+                            if (a.tsb) a.tsb[i] = (int8_t)(site ? sgn : 0);
+                        } else {
+                            const int sg = (kc & 3) == 1 ? 1 : ((kc & 3) == 3 ? -1 : 0);
+                            if (a.ts) a.ts[i] = (int8_t)sg;
+                            if (a.td1) {
+                                const uint32_t w = a.w1[i];
+                                a.td1[i] = (w == QAI_WORD_INF) ? -1 : (int32_t)word_d2(w);
+                            }
+                            if (a.tb2) a.tb2[i] = site ? 1 : 0;
+                        }
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                int next = -1;
+                for (int c = nch - 1; c >= 0; --c) {
+                    const uint64_t m = masks[c];
+                    const int cl = carry[c];
+                    const int x = c * 64 + lane;
+                    const int hb = highest_at_or_below(m, lane);
+                    const int lb = lowest_at_or_above(m, lane);
+                    const int L = hb >= 0 ? c * 64 + hb : cl;
+                    const int R = lb >= 0 ? c * 64 + lb : next;
+                    uint32_t word = QAI_WORD_INF;
+                    if (L >= 0 || R >= 0) {
+                        const int dl = L >= 0 ? x - L : 0x7fffffff;
+                        const int dr = R >= 0 ? R - x : 0x7fffffff;
+                        const int st = (dl <= dr) ? L : R;
+                        const uint32_t d = (uint32_t)(dl <= dr ? dl : dr);
+                        const uint32_t code = (MODE == 0) ? (uint32_t)codes[st] : 0u;
+                        word = word_make(d * d, code);
+                    }
+                    if (x < nx)
+                        a.wout[base + x] = word;
+                    if (m)
+                        next = c * 64 + __ffsll((unsigned long long)m) - 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (MODE == 0 && __ballot(bad) && lane == 0)
+            atomicOr(a.status, QAI_STATUS_QRANGE);
     }
 }
 
@@ -233,17 +420,22 @@ __global__ __launch_bounds__(256) void k_env_window(EnvArgs a)
         const int64_t x0 = xb << txl;
         const int64_t base = (AXIS == 1) ? o * a.nx * a.ny + x0 : o * a.nx + x0;
         __syncthreads();
+        int any = 0;
         for (int i = threadIdx.x; i < total; i += blockDim.x) {
             const int r = i >> txl, c = i & (Tx - 1);
-            tile[i] = (x0 + c < a.nx) ? a.w[base + (int64_t)r * stride + c] : QAI_WORD_INF;
+            const uint32_t v = (x0 + c < a.nx) ? a.win[base + (int64_t)r * stride + c] : QAI_WORD_INF;
+            tile[i] = v;
+            any |= (v != QAI_WORD_INF);
         }
-        __syncthreads();
+        // a tile without any site (e.g. the domain's edge planes in the first EDT)
+        // keeps every voxel at "no site": skip the searches
+        const bool live = __syncthreads_or(any) != 0;
         for (int i = threadIdx.x; i < total; i += blockDim.x) {
             const int r = i >> txl, c = i & (Tx - 1);
             if (x0 + c >= a.nx)
                 continue;
             uint32_t best = tile[i];
-            for (int d = 1; d < n; ++d) {
+            for (int d = 1; live && d < n; ++d) {
                 const uint32_t d2s = (uint32_t)d * (uint32_t)d << 2;
                 if (d2s > (best | 3u))
                     break;
@@ -270,53 +462,6 @@ __global__ __launch_bounds__(256) void k_env_window(EnvArgs a)
     }
 }
 
-// Banded exact lower envelope (the result of Algorithm 1 on every line of a
-// tile, computed with all threads of the workgroup).
-//
-// A tile is Tx adjacent x-columns by the whole line along the pass axis,
-// staged in LDS.  Each line is cut into bands of m positions, one thread per
-// (column, band):
-//   1. every thread builds the lower envelope of the sites of its band with
-//      Algorithm 1's stack (RemoveEDT), kept as a doubly linked list in LDS;
-//   2. log2(bands) levels merge neighbouring envelopes pairwise: the left
-//      list's tail and the right list's head are trimmed with the same
-//      predicate until both junction triples are kept;
-//   3. every thread walks to the site owning its first position (values
-//      along the list are unimodal there) and advances monotonically through
-//      its band, keeping the lower site on equal values.
-// Removed sites are strictly dominated everywhere, so the survivors and the
-// chosen sites are exactly those of Algorithm 1's stack and query.
-struct BandLds {
-    uint32_t* G;    // [n][Tx] packed words of the sites (QAI_WORD_INF: none)
-    int16_t* PREV;  // [n][Tx] list links; -2 marks a removed site
-    int16_t* NEXT;  // [n][Tx]
-    int16_t* HEAD;  // [B][Tx] first / last element of a (merged) band list
-    int16_t* TAIL;
-    int16_t* FIRST; // [B][Tx] first / last surviving site inside each band
-    int16_t* LAST;
-    unsigned long long* MASK; // [Tx] bands holding a survivor
-};
-
-__device__ __forceinline__ size_t band_lds_bytes(int n, int B, int Tx)
-{
-    return (size_t)n * Tx * 8 + (size_t)B * Tx * 8 + (size_t)Tx * 8 + 64;
-}
-
-__device__ __forceinline__ BandLds band_lds(unsigned char* smem, int n, int B, int Tx)
-{
-    BandLds L;
-    unsigned long long* mask = (unsigned long long*)smem;
-    L.MASK = mask;
-    L.G = (uint32_t*)(smem + (size_t)Tx * 8);
-    L.PREV = (int16_t*)(L.G + (size_t)n * Tx);
-    L.NEXT = L.PREV + (size_t)n * Tx;
-    L.HEAD = L.NEXT + (size_t)n * Tx;
-    L.TAIL = L.HEAD + (size_t)B * Tx;
-    L.FIRST = L.TAIL + (size_t)B * Tx;
-    L.LAST = L.FIRST + (size_t)B * Tx;
-    return L;
-}
-
 // RemoveEDT(g_u, g_v, g_w, u, v) with sites u < v < w (Section III-B): true
 // when v's cell between u and w is empty.  Products reach 2^44: int64.
 __device__ __forceinline__ bool remove_mid(uint32_t gu, uint32_t gv, uint32_t gw, int u, int v, int w)
@@ -329,185 +474,6 @@ __device__ __forceinline__ uint32_t fval(uint32_t g, int s, int p)
 {
     const int d = p - s;
     return g + (uint32_t)(d * d);
-}
-
-template <int AXIS, bool EPI>
-__global__ __launch_bounds__(1024) void k_env_band(EnvArgs a, int m, int B)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int txl = a.tx_log2;
-    const int Tx = 1 << txl;
-    const int n = (int)((AXIS == 1) ? a.ny : a.nz);
-    const int64_t stride = (AXIS == 1) ? a.nx : a.nx * a.ny;
-    const int64_t nxb = (a.nx + Tx - 1) >> txl;
-    const int total = n << txl;
-    BandLds L = band_lds(smem, n, B, Tx);
-    const int tid = threadIdx.x;
-    const int c = tid & (Tx - 1);
-    const int b = tid >> txl;
-    const bool active = b < B;
-    const int p0 = b * m;
-    const int p1 = min(n, p0 + m);
-
-    for (uint64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        const uint64_t tl = xcd_remap(t, a.ntiles);
-        const int64_t xb = (int64_t)(tl % (uint64_t)nxb), o = (int64_t)(tl / (uint64_t)nxb);
-        const int64_t x0 = xb << txl;
-        const int64_t base = (AXIS == 1) ? o * a.nx * a.ny + x0 : o * a.nx + x0;
-        __syncthreads();
-        for (int i = tid; i < total; i += blockDim.x) {
-            const int r = i >> txl, cc = i & (Tx - 1);
-            L.G[i] = (x0 + cc < a.nx) ? a.w[base + (int64_t)r * stride + cc] : QAI_WORD_INF;
-        }
-        if (tid < Tx)
-            L.MASK[tid] = 0ull;
-        __syncthreads();
-
-        // 1. envelope of each band
-        if (active) {
-            int top = -1, second = -1, head = -1;
-            uint32_t gtop = 0, gsec = 0;
-            for (int p = p0; p < p1; ++p) {
-                const uint32_t w = L.G[(p << txl) + c];
-                if (w == QAI_WORD_INF)
-                    continue;
-                const uint32_t g = w >> 2;
-                for (int it = 0; it < m && second >= 0 && remove_mid(gsec, gtop, g, second, top, p); ++it) {
-                    L.PREV[(top << txl) + c] = -2;
-                    top = second;
-                    gtop = gsec;
-                    second = L.PREV[(second << txl) + c];
-                    gsec = second >= 0 ? (L.G[(second << txl) + c] >> 2) : 0u;
-                }
-                L.PREV[(p << txl) + c] = (int16_t)top;
-                if (top >= 0)
-                    L.NEXT[(top << txl) + c] = (int16_t)p;
-                else
-                    head = p;
-                second = top;
-                gsec = gtop;
-                top = p;
-                gtop = g;
-            }
-            if (top >= 0)
-                L.NEXT[(top << txl) + c] = -1;
-            L.HEAD[(b << txl) + c] = (int16_t)head;
-            L.TAIL[(b << txl) + c] = (int16_t)top;
-        }
-        __syncthreads();
-
-        // 2. pairwise merges
-        for (int span = 1; span < B; span <<= 1) {
-            if (active && (b & (2 * span - 1)) == 0 && b + span < B) {
-                const int r = b + span;
-                const int tl_ = L.TAIL[(b << txl) + c];
-                const int tr = L.TAIL[(r << txl) + c];
-                if (tl_ < 0) {
-                    L.HEAD[(b << txl) + c] = L.HEAD[(r << txl) + c];
-                    L.TAIL[(b << txl) + c] = (int16_t)tr;
-                } else if (tr >= 0) {
-                    int t1 = tl_, t0 = L.PREV[(t1 << txl) + c];
-                    int h1 = L.HEAD[(r << txl) + c], h2 = L.NEXT[(h1 << txl) + c];
-                    uint32_t g_t1 = L.G[(t1 << txl) + c] >> 2, g_h1 = L.G[(h1 << txl) + c] >> 2;
-                    uint32_t g_t0 = t0 >= 0 ? (L.G[(t0 << txl) + c] >> 2) : 0u;
-                    uint32_t g_h2 = h2 >= 0 ? (L.G[(h2 << txl) + c] >> 2) : 0u;
-                    for (int it = 0; it < n; ++it) {
-                        if (t0 >= 0 && remove_mid(g_t0, g_t1, g_h1, t0, t1, h1)) {
-                            L.PREV[(t1 << txl) + c] = -2;
-                            t1 = t0;
-                            g_t1 = g_t0;
-                            t0 = L.PREV[(t0 << txl) + c];
-                            g_t0 = t0 >= 0 ? (L.G[(t0 << txl) + c] >> 2) : 0u;
-                            continue;
-                        }
-                        if (h2 >= 0 && remove_mid(g_t1, g_h1, g_h2, t1, h1, h2)) {
-                            L.PREV[(h1 << txl) + c] = -2;
-                            h1 = h2;
-                            g_h1 = g_h2;
-                            h2 = L.NEXT[(h2 << txl) + c];
-                            g_h2 = h2 >= 0 ? (L.G[(h2 << txl) + c] >> 2) : 0u;
-                            continue;
-                        }
-                        break;
-                    }
-                    L.NEXT[(t1 << txl) + c] = (int16_t)h1;
-                    L.PREV[(h1 << txl) + c] = (int16_t)t1;
-                    L.TAIL[(b << txl) + c] = (int16_t)tr;
-                }
-            }
-            __syncthreads();
-        }
-
-        // survivors inside each band
-        if (active) {
-            int first = -1, last = -1;
-            for (int p = p0; p < p1; ++p) {
-                const int i = (p << txl) + c;
-                if (L.G[i] != QAI_WORD_INF && L.PREV[i] != -2) {
-                    if (first < 0)
-                        first = p;
-                    last = p;
-                }
-            }
-            L.FIRST[(b << txl) + c] = (int16_t)first;
-            L.LAST[(b << txl) + c] = (int16_t)last;
-            if (first >= 0)
-                atomicOr(&L.MASK[c], 1ull << b);
-        }
-        __syncthreads();
-
-        // 3. query
-        if (active && x0 + c < a.nx) {
-            const unsigned long long mk = L.MASK[c];
-            int s = L.FIRST[(b << txl) + c];
-            if (s < 0 && mk) {
-                const unsigned long long below = (b == 0) ? 0ull : (mk & ((1ull << b) - 1ull));
-                if (below)
-                    s = L.LAST[((63 - __clzll(below)) << txl) + c];
-                else
-                    s = L.FIRST[((__ffsll(mk) - 1) << txl) + c];
-            }
-            if (s < 0) {
-                for (int p = p0; p < p1; ++p) {
-                    const int64_t gi = base + (int64_t)p * stride + c;
-                    if (a.write_words)
-                        a.w[gi] = QAI_WORD_INF;
-                    if (EPI)
-                        interp_store(gi, QAI_WORD_INF, a.w1, a.xq, a.out, a.eta_eb, a.power, a.td2, a.tw);
-                }
-            } else {
-                int o = s;
-                uint32_t wo = L.G[(o << txl) + c];
-                for (int it = 0; it < n; ++it) {
-                    const int pv = L.PREV[(o << txl) + c];
-                    if (pv < 0)
-                        break;
-                    const uint32_t wp = L.G[(pv << txl) + c];
-                    if (fval(wp >> 2, pv, p0) > fval(wo >> 2, o, p0))
-                        break;
-                    o = pv;
-                    wo = wp;
-                }
-                int nx_ = L.NEXT[(o << txl) + c];
-                uint32_t wn = nx_ >= 0 ? L.G[(nx_ << txl) + c] : 0u;
-                for (int p = p0; p < p1; ++p) {
-                    for (int it = 0; it < n && nx_ >= 0 && fval(wn >> 2, nx_, p) < fval(wo >> 2, o, p); ++it) {
-                        o = nx_;
-                        wo = wn;
-                        nx_ = L.NEXT[(o << txl) + c];
-                        wn = nx_ >= 0 ? L.G[(nx_ << txl) + c] : 0u;
-                    }
-                    const int d = p - o;
-                    const uint32_t word = wo + ((uint32_t)(d * d) << 2);
-                    const int64_t gi = base + (int64_t)p * stride + c;
-                    if (a.write_words)
-                        a.w[gi] = word;
-                    if (EPI)
-                        interp_store(gi, word, a.w1, a.xq, a.out, a.eta_eb, a.power, a.td2, a.tw);
-                }
-            }
-        }
-    }
 }
 
 // Wave-per-column variant of the banded envelope.  The B bands of a column
@@ -562,7 +528,7 @@ __global__ __launch_bounds__(1024) void k_env_band2(EnvArgs a, int lb)
         __syncthreads();
         for (int i = tid; i < total; i += blockDim.x) {
             const int r = i >> txl, cc = i & (Tx - 1);
-            L.G[L.at(cc, r)] = (x0 + cc < a.nx) ? a.w[base + (int64_t)r * stride + cc] : QAI_WORD_INF;
+            L.G[L.at(cc, r)] = (x0 + cc < a.nx) ? a.win[base + (int64_t)r * stride + cc] : QAI_WORD_INF;
         }
         for (int i = tid; i < ((B * M - n) << txl); i += blockDim.x) // padding positions n .. B*M-1
             L.G[L.at(i & (Tx - 1), n + (i >> txl))] = QAI_WORD_INF;
@@ -727,6 +693,230 @@ __global__ __launch_bounds__(1024) void k_env_band2(EnvArgs a, int lb)
     }
 }
 
+// RemoveEDT in 32 bits with full-rate 24-bit multiplies: exact when the line
+// length n < 2^12 and every site value g < 2^24 satisfy n g + n^3 / 4 < 2^31
+// (with a + b = c <= n the positive term c g_v is below n g and the negative
+// ones sum below n g + n^3 / 4).  The launcher checks this from the extents.
+__device__ __forceinline__ bool remove_mid24(uint32_t gu, uint32_t gv, uint32_t gw, int u, int v, int w)
+{
+    const uint32_t a = (uint32_t)(v - u), b = (uint32_t)(w - v), c = (uint32_t)(w - u);
+    const int32_t t = (int32_t)__umul24(c, gv) - (int32_t)__umul24(b, gu) - (int32_t)__umul24(a, gw) -
+                      (int32_t)__umul24(__umul24(a, b), c);
+    return t > 0;
+}
+
+template <bool SMALL>
+__device__ __forceinline__ bool remove_sel(uint32_t gu, uint32_t gv, uint32_t gw, int u, int v, int w)
+{
+    if (SMALL)
+        return remove_mid24(gu, gv, gw, u, v, w);
+    return remove_mid(gu, gv, gw, u, v, w);
+}
+
+__device__ __forceinline__ uint32_t sq24(int d) { return (uint32_t)__mul24(d, d); }
+
+// Streaming exact lower envelope: one lane per column, 64 adjacent x-columns
+// per wavefront, one sweep along the line (Algorithm 1 made online).
+//
+// At row i the lane pushes site i on Algorithm 1's stack (popping with
+// RemoveEDT), then emits every row e whose answer can no longer change: a
+// future site j > i contributes at least (j - e)^2 >= (i+1-e)^2, so e is
+// final once its best value is <= (i+1-e)^2 (a future site of equal value
+// has the higher coordinate and loses the tie).  A finalised owner cannot be
+// removed later (it would have to be strictly dominated at e), so everything
+// below the query pointer is dropped and only the live window
+// [owner(e), top] is kept, in an LDS ring of C entries per lane.  Emission is
+// synchronised per group of 16 lanes, so stores are 64-byte row segments
+// while the live window only has to cover the group's slowest column.  A
+// column whose window outgrows the ring is finished afterwards by the whole
+// wave with an exact outward search over the untouched input column (same
+// result, different cost).
+template <int AXIS, int C, bool SMALL>
+__global__ __launch_bounds__(128) void k_env_stream(EnvArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int nwv = blockDim.x >> 6;
+    uint32_t* rw = (uint32_t*)smem + (size_t)wv * C * 64;
+    uint16_t* rh = (uint16_t*)((uint32_t*)smem + (size_t)nwv * C * 64) + (size_t)wv * C * 64;
+    const int n = (int)((AXIS == 1) ? a.ny : a.nz);
+    const int64_t stride = (AXIS == 1) ? a.nx : a.nx * a.ny;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    const uint64_t ngroups = (a.ntiles + nwv - 1) / nwv;
+    const int grp = lane >> 4;
+    const uint64_t gmask = 0xFFFFull << (grp * 16);
+
+    for (uint64_t t = blockIdx.x; t < ngroups; t += gridDim.x) {
+        const uint64_t tile = (uint64_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(t, ngroups) * nwv + wv));
+        if (tile >= a.ntiles)
+            continue;
+        const int64_t xb = (int64_t)(tile % (uint64_t)nxb), o = (int64_t)(tile / (uint64_t)nxb);
+        const int64_t x0 = xb * 64;
+        const bool valid = x0 + lane < a.nx;
+        const int col = valid ? lane : 0; // invalid lanes read a valid word and ignore it
+        const int64_t tb = ((AXIS == 1) ? o * a.nx * a.ny : o * a.nx) + x0;
+        const uint32_t* __restrict__ inp = a.win + tb;
+        uint32_t* __restrict__ outp = a.w + tb;
+
+        int lo = 0, top = -1;
+        uint32_t wtop = 0, wsec = 0, wlo = 0, wlo1 = 0;
+        int htop = 0, hsec = 0, hlo = 0, hlo1 = 0;
+        bool ovf = !valid;
+        int e = 0; // next row to emit (uniform within the lane's group)
+
+        uint32_t cur[8], nxt[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            cur[k] = inp[(int64_t)min(k, n - 1) * stride + col];
+        for (int i0 = 0; i0 < n; i0 += 8) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                nxt[k] = inp[(int64_t)min(i0 + 8 + k, n - 1) * stride + col];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int i = i0 + k;
+                if (i >= n)
+                    break;
+                const uint32_t w = cur[k];
+                if (w != QAI_WORD_INF && !ovf) {
+                    const uint32_t g = w >> 2;
+                    for (int it = 0; it < C && top > lo; ++it) {
+                        if (!remove_sel<SMALL>(wsec >> 2, wtop >> 2, g, hsec, htop, i))
+                            break;
+                        --top;
+                        wtop = wsec;
+                        htop = hsec;
+                        if (top > lo) {
+                            const int sl = ((top - 1) & (C - 1)) * 64 + lane;
+                            wsec = rw[sl];
+                            hsec = rh[sl];
+                        }
+                    }
+                    if (top - lo + 1 >= C) {
+                        ovf = true;
+                    } else {
+                        ++top;
+                        const int sl = (top & (C - 1)) * 64 + lane;
+                        rw[sl] = w;
+                        rh[sl] = (uint16_t)i;
+                        wsec = wtop;
+                        hsec = htop;
+                        wtop = w;
+                        htop = i;
+                        if (top == lo) {
+                            wlo = w;
+                            hlo = i;
+                        } else if (top == lo + 1) {
+                            wlo1 = w;
+                            hlo1 = i;
+                        }
+                    }
+                }
+                for (int guard = 0; guard <= n; ++guard) {
+                    bool ok = false;
+                    uint32_t word = QAI_WORD_INF;
+                    if (e <= i) {
+                        if (ovf) {
+                            ok = true;
+                        } else if (top >= lo) {
+                            for (int it = 0; it < C && lo < top; ++it) {
+                                if (!((wlo1 >> 2) + sq24(e - hlo1) < (wlo >> 2) + sq24(e - hlo)))
+                                    break;
+                                ++lo;
+                                wlo = wlo1;
+                                hlo = hlo1;
+                                if (lo < top) {
+                                    const int sl = ((lo + 1) & (C - 1)) * 64 + lane;
+                                    wlo1 = rw[sl];
+                                    hlo1 = rh[sl];
+                                }
+                            }
+                            const uint32_t d2 = sq24(e - hlo);
+                            ok = (wlo >> 2) + d2 <= sq24(i + 1 - e);
+                            word = wlo + (d2 << 2);
+                        }
+                    }
+                    const bool emit = (__ballot(ok) & gmask) == gmask;
+                    if (__ballot(emit) == 0ull)
+                        break;
+                    if (emit) {
+                        if (!ovf)
+                            outp[(int64_t)e * stride + lane] = word;
+                        ++e;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                cur[k] = nxt[k];
+        }
+        // every remaining row is final
+        for (; e < n; ++e) {
+            if (!ovf) {
+                uint32_t word = QAI_WORD_INF;
+                if (top >= lo) {
+                    for (int it = 0; it < C && lo < top; ++it) {
+                        if (!((wlo1 >> 2) + sq24(e - hlo1) < (wlo >> 2) + sq24(e - hlo)))
+                            break;
+                        ++lo;
+                        wlo = wlo1;
+                        hlo = hlo1;
+                        if (lo < top) {
+                            const int sl = ((lo + 1) & (C - 1)) * 64 + lane;
+                            wlo1 = rw[sl];
+                            hlo1 = rh[sl];
+                        }
+                    }
+                    word = wlo + (sq24(e - hlo) << 2);
+                }
+                outp[(int64_t)e * stride + lane] = word;
+            }
+        }
+
+        // columns whose live window outgrew the ring: exact outward search,
+        // one column at a time by the whole wave, staged in the ring's LDS
+        uint64_t om = __ballot(ovf && valid);
+        const bool staged = n <= C * 64;
+        while (om) {
+            const int l = __ffsll((unsigned long long)om) - 1;
+            om &= om - 1ull;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (staged)
+                for (int r = lane; r < n; r += 64)
+                    rw[r] = inp[(int64_t)r * stride + l];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int p = lane; p < n; p += 64) {
+                uint32_t best = staged ? rw[p] : inp[(int64_t)p * stride + l];
+                for (int r = 1; r < n; ++r) {
+                    const uint32_t r2 = (uint32_t)r * (uint32_t)r << 2;
+                    if (r2 > (best | 3u))
+                        break;
+                    const int l0 = p - r, h0 = p + r;
+                    if (l0 < 0 && h0 >= n)
+                        break;
+                    if (l0 >= 0) {
+                        const uint32_t cand = word_add(staged ? rw[l0] : inp[(int64_t)l0 * stride + l], r2);
+                        if ((cand >> 2) <= (best >> 2))
+                            best = cand;
+                    }
+                    if (h0 < n) {
+                        const uint32_t cand = word_add(staged ? rw[h0] : inp[(int64_t)h0 * stride + l], r2);
+                        if ((cand >> 2) < (best >> 2))
+                            best = cand;
+                    }
+                }
+                outp[(int64_t)p * stride + l] = best;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 __global__ void k_clear(uint32_t* p, int n)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -748,11 +938,16 @@ void default_tuning(Tuning& t)
     for (int i = 0; i < 3; ++i) {
         t.env_tx_log2[i] = -1;
         t.env_algo[i] = 0;
+        t.edt1_algo[i] = 1;
+        t.stream_cap[i] = 32;
+        t.edt1_cap[i] = 16;
     }
     t.env_threads = 256;
+    t.seed_ty = 4;
+    t.seed_tz = 16;
 }
 
-hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s)
+static hipError_t launch_seed_lines(int mode, const SeedArgs& in, hipStream_t s)
 {
     SeedArgs a = in;
     const int64_t nch = (a.nx + 63) / 64;
@@ -772,6 +967,42 @@ hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s)
     return hipGetLastError();
 }
 
+static size_t slab_bytes(int64_t nx, int ty, int rows, int planes)
+{
+    const int64_t nch = (nx + 63) / 64;
+    const size_t ring = ((size_t)planes * rows * nx * 4 + 15) & ~(size_t)15;
+    return ring + (size_t)ty * nch * (64 + 8 + 4) + 64;
+}
+
+hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s, int want_ty, int want_tz)
+{
+    const int planes = in.nz > 1 ? 3 : 1;
+    int ty = want_ty > 0 ? want_ty : 4;
+    if (in.ny == 1)
+        ty = 1;
+    auto rows_of = [&](int t) { return in.ny > 1 ? t + 2 : 1; };
+    while (ty > 1 && slab_bytes(in.nx, ty, rows_of(ty), planes) > 96 * 1024)
+        ty >>= 1;
+    if (slab_bytes(in.nx, ty, rows_of(ty), planes) > 96 * 1024)
+        return launch_seed_lines(mode, in, s); // very long x-lines: one line per wave
+    SlabArgs A;
+    A.s = in;
+    A.ty = ty;
+    A.rows = rows_of(ty);
+    A.planes = planes;
+    A.tz = in.nz > 1 ? (want_tz > 0 ? want_tz : 16) : 1;
+    A.nby = (in.ny + ty - 1) / ty;
+    A.nbz = (in.nz + A.tz - 1) / A.tz;
+    const size_t lds = slab_bytes(in.nx, ty, A.rows, planes);
+    const uint32_t grid = grid_cap((uint64_t)(A.nby * A.nbz), 1u << 20);
+    const int threads = 64 * (ty < 4 ? 4 : ty);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_seed_slab<0>, dim3(grid), dim3(threads), lds, s, A);
+    else
+        hipLaunchKernelGGL(k_seed_slab<1>, dim3(grid), dim3(threads), lds, s, A);
+    return hipGetLastError();
+}
+
 static int default_tx_log2(int64_t n)
 {
     // windowed variant: keep the staged tile within 32 KB
@@ -780,42 +1011,6 @@ static int default_tx_log2(int64_t n)
         --l;
     return l;
 }
-
-static size_t band_bytes(int n, int B, int Tx)
-{
-    return (size_t)n * Tx * 8 + (size_t)B * Tx * 8 + (size_t)Tx * 8 + 64;
-}
-
-// Band geometry of a line of n positions: at most 64 bands of m positions,
-// Tx columns per tile so that the LDS image stays within about 80 KB (two
-// workgroups per CU), never below one column.
-void band_geometry(int n, int want_txl, int& m, int& B, int& txl, size_t& lds)
-{
-    m = (n + 63) / 64;
-    if (m < 1)
-        m = 1;
-    B = (n + m - 1) / m;
-    txl = want_txl >= 0 ? want_txl : 4;
-    while (txl > 0 && band_bytes(n, B, 1 << txl) > 80 * 1024)
-        --txl;
-    lds = band_bytes(n, B, 1 << txl);
-}
-
-template <int AXIS, bool EPI>
-static hipError_t launch_band_t(EnvArgs a, int m, int B, size_t lds, int threads, uint32_t grid, hipStream_t s)
-{
-    static bool attr_done = false;
-    if (lds > 64 * 1024 && !attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_env_band<AXIS, EPI>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds < 160 * 1024 ? 160 * 1024 : (int)lds);
-        if (e != hipSuccess)
-            return e;
-        attr_done = true;
-    }
-    hipLaunchKernelGGL((k_env_band<AXIS, EPI>), dim3(grid), dim3(threads), lds, s, a, m, B);
-    return hipGetLastError();
-}
-
 
 template <int AXIS, bool EPI, int M>
 static hipError_t launch_band2_t(EnvArgs a, int lb, size_t lds, int threads, uint32_t grid, hipStream_t s)
@@ -838,15 +1033,14 @@ static hipError_t launch_band2_m(EnvArgs a, int M, int lb, size_t lds, int threa
     switch (M) {
     case 8: return launch_band2_t<AXIS, EPI, 8>(a, lb, lds, threads, grid, s);
     case 16: return launch_band2_t<AXIS, EPI, 16>(a, lb, lds, threads, grid, s);
-    case 32: return launch_band2_t<AXIS, EPI, 32>(a, lb, lds, threads, grid, s);
-    default: return launch_band2_t<AXIS, EPI, 64>(a, lb, lds, threads, grid, s);
+    default: return launch_band2_t<AXIS, EPI, 32>(a, lb, lds, threads, grid, s);
     }
 }
 
-// Geometry of the wave-per-column variant: bands of M = max(8, 2^k) positions
-// with at most 64 bands, B = 2^lb bands per column, Tx columns per tile
-// (the LDS image is 8 bytes per padded position).
-void band2_geometry(int n, int want_txl, int& M, int& lb, int& txl, size_t& lds)
+// Geometry of the wave-per-column banded variant: bands of M = max(8, 2^k)
+// positions with at most 64 bands, B = 2^lb bands per column, Tx columns per
+// tile (the LDS image is 8 bytes per padded position).
+static void band2_geometry(int n, int want_txl, int& M, int& lb, int& txl, size_t& lds)
 {
     M = 8;
     while (M * 64 < n)
@@ -861,13 +1055,12 @@ void band2_geometry(int n, int want_txl, int& M, int& lb, int& txl, size_t& lds)
         --txl;
     while (txl > 0 && (size_t)(B * (M + 1) + 1) * (1 << txl) * 8 > 80 * 1024)
         --txl;
-    // a tile must fill whole wavefronts: Tx * B >= 64
     while ((B << txl) < 64)
         ++txl;
     lds = (size_t)(B * (M + 1) + 1) * (1 << txl) * 8;
 }
 
-hipError_t launch_band2(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_t s)
+static hipError_t launch_band2(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_t s)
 {
     const int n = (int)(axis == 1 ? a.ny : a.nz);
     int M, lb, txl;
@@ -883,6 +1076,27 @@ hipError_t launch_band2(int axis, bool epi, EnvArgs a, const Tuning& t, hipStrea
                    : launch_band2_m<1, false>(a, M, lb, lds, threads, grid, s);
     return epi ? launch_band2_m<2, true>(a, M, lb, lds, threads, grid, s)
                : launch_band2_m<2, false>(a, M, lb, lds, threads, grid, s);
+}
+
+template <int AXIS, int C>
+static hipError_t launch_stream_t(EnvArgs a, hipStream_t s)
+{
+    // LDS ring: 6 bytes x C entries x 64 lanes per wave
+    const int waves = C >= 32 ? 1 : 2;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    a.ntiles = (uint64_t)(nxb * (AXIS == 1 ? a.nz : a.ny));
+    const uint64_t groups = (a.ntiles + waves - 1) / waves;
+    const size_t lds = (size_t)waves * C * 64 * 6;
+    const int64_t n = AXIS == 1 ? a.ny : a.nz;
+    // site values are squared distances within the lower dimensions
+    const int64_t gmax = (a.nx - 1) * (a.nx - 1) + (AXIS == 2 ? (a.ny - 1) * (a.ny - 1) : 0);
+    const bool small = n < 4096 && gmax < (1 << 24) && n * gmax + n * n * n / 4 < (int64_t)1 << 31;
+    const dim3 grid(grid_cap(groups, 1u << 20)), blk(64 * waves);
+    if (small)
+        hipLaunchKernelGGL((k_env_stream<AXIS, C, true>), grid, blk, lds, s, a);
+    else
+        hipLaunchKernelGGL((k_env_stream<AXIS, C, false>), grid, blk, lds, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_t s)
@@ -907,21 +1121,16 @@ hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_
         }
         return hipGetLastError();
     }
-    if (n <= 64 * 32 && t.env_algo[axis] != 2)
+    if (t.env_algo[axis] == 2 && n <= 64 * 32)
         return launch_band2(axis, epi, a, t, s);
-    int m, B, txl;
-    size_t lds;
-    band_geometry((int)n, t.env_tx_log2[axis], m, B, txl, lds);
-    a.tx_log2 = txl;
-    const int64_t nxb = (a.nx + (1 << txl) - 1) >> txl;
-    a.ntiles = (uint64_t)(nxb * (axis == 1 ? a.nz : a.ny));
-    const uint32_t grid = grid_cap(a.ntiles, 1u << 20);
-    int threads = ((B << txl) + 63) / 64 * 64;
+    if (epi)
+        return hipErrorInvalidValue; // the streaming pass never carries step E
+    const int cap = t.stream_cap[axis] <= 16 ? 16 : (t.stream_cap[axis] <= 32 ? 32 : 64);
     if (axis == 1)
-        return epi ? launch_band_t<1, true>(a, m, B, lds, threads, grid, s)
-                   : launch_band_t<1, false>(a, m, B, lds, threads, grid, s);
-    return epi ? launch_band_t<2, true>(a, m, B, lds, threads, grid, s)
-               : launch_band_t<2, false>(a, m, B, lds, threads, grid, s);
+        return cap == 16 ? launch_stream_t<1, 16>(a, s)
+                         : (cap == 32 ? launch_stream_t<1, 32>(a, s) : launch_stream_t<1, 64>(a, s));
+    return cap == 16 ? launch_stream_t<2, 16>(a, s)
+                     : (cap == 32 ? launch_stream_t<2, 32>(a, s) : launch_stream_t<2, 64>(a, s));
 }
 
 hipError_t launch_interp(const InterpArgs& a, hipStream_t s)
@@ -937,6 +1146,28 @@ hipError_t launch_clear(uint32_t* p, int n, hipStream_t s)
     return hipGetLastError();
 }
 
+// Which of the three word buffers ends up holding the final words of the
+// first EDT (w1) and of the second (w2): the first EDT ping-pongs between
+// buffers 0 and 1, the second between the two buffers w1 does not occupy.
+void final_buffers(int64_t nz, int64_t ny, int64_t nx, int& w1, int& w2)
+{
+    (void)nx;
+    int cur = 0;
+    if (ny > 1)
+        cur ^= 1;
+    if (nz > 1)
+        cur ^= 1;
+    w1 = cur;
+    const int o0 = w1 == 0 ? 1 : 0;
+    const int o1 = w1 == 2 ? 1 : 2;
+    int c2 = o0;
+    if (ny > 1)
+        c2 = (c2 == o0) ? o1 : o0;
+    if (nz > 1)
+        c2 = (c2 == o0) ? o1 : o0;
+    w2 = c2;
+}
+
 #define QAI_TRY(expr)                   \
     do {                                \
         hipError_t e_ = (expr);         \
@@ -944,16 +1175,15 @@ hipError_t launch_clear(uint32_t* p, int n, hipStream_t s)
             return e_;                  \
     } while (0)
 
-hipError_t run_plain(const Plan1& p, const Tuning& t, hipStream_t s)
+hipError_t run_plain(Plan1& p, const Tuning& t, hipStream_t s)
 {
-    const float eta_eb = p.eta * p.eb;
+    uint32_t* buf[3] = {p.bufA, p.bufB, p.bufC};
     prof_begin("clear", s);
     QAI_TRY(launch_clear(p.status, 1, s));
     prof_end(s);
 
     SeedArgs sa = {};
     sa.xq = p.xq;
-    sa.w1 = p.w1;
     sa.nx = p.nx;
     sa.ny = p.ny;
     sa.nz = p.nz;
@@ -968,9 +1198,10 @@ hipError_t run_plain(const Plan1& p, const Tuning& t, hipStream_t s)
     sa.tb2 = p.taps.b2;
 
     // step A + x pass of step B
-    sa.wout = p.w1;
+    int cur = 0;
+    sa.wout = buf[cur];
     prof_begin("seed1_xscan", s);
-    QAI_TRY(launch_seed(0, sa, s));
+    QAI_TRY(launch_seed(0, sa, s, t.seed_ty, t.seed_tz));
     prof_end(s);
 
     EnvArgs ea = {};
@@ -978,54 +1209,65 @@ hipError_t run_plain(const Plan1& p, const Tuning& t, hipStream_t s)
     ea.ny = p.ny;
     ea.nz = p.nz;
     ea.write_words = true;
-    ea.w = p.w1;
+    Tuning t1 = t; // the first EDT: dense boundaries, short owner distances
+    for (int i = 0; i < 3; ++i) {
+        t1.stream_cap[i] = t.edt1_cap[i];
+        t1.env_algo[i] = t.edt1_algo[i];
+    }
     if (p.ny > 1) {
+        ea.win = buf[cur];
+        ea.w = buf[cur ^ 1];
         prof_begin("edt1_y", s);
-        QAI_TRY(launch_env(1, false, ea, t, s));
+        QAI_TRY(launch_env(1, false, ea, t1, s));
         prof_end(s);
+        cur ^= 1;
     }
     if (p.nz > 1) {
+        ea.win = buf[cur];
+        ea.w = buf[cur ^ 1];
         prof_begin("edt1_z", s);
-        QAI_TRY(launch_env(2, false, ea, t, s));
+        QAI_TRY(launch_env(2, false, ea, t1, s));
         prof_end(s);
+        cur ^= 1;
     }
+    const int w1 = cur;
 
     // step C + x pass of step D
-    sa.wout = p.w2;
+    const int o0 = w1 == 0 ? 1 : 0, o1 = w1 == 2 ? 1 : 2;
+    int c2 = o0;
+    sa.w1 = buf[w1];
+    sa.wout = buf[c2];
     prof_begin("seed2_xscan", s);
-    QAI_TRY(launch_seed(1, sa, s));
+    QAI_TRY(launch_seed(1, sa, s, t.seed_ty, t.seed_tz));
     prof_end(s);
 
-    // remaining passes of step D; the last one carries step E
-    ea.w = p.w2;
-    ea.w1 = p.w1;
-    ea.xq = p.xq;
-    ea.out = p.out;
-    ea.eta_eb = eta_eb;
-    ea.power = p.power;
-    ea.td2 = p.taps.d2sq;
-    ea.tw = p.taps.w;
-    if (p.nz > 1) {
-        if (p.ny > 1) {
-            prof_begin("edt2_y", s);
-            QAI_TRY(launch_env(1, false, ea, t, s));
-            prof_end(s);
-        }
-        ea.write_words = p.keep_w2;
-        prof_begin("edt2_z_interp", s);
-        QAI_TRY(launch_env(2, true, ea, t, s));
+    // remaining passes of step D
+    if (p.ny > 1) {
+        const int nx2 = (c2 == o0) ? o1 : o0;
+        ea.win = buf[c2];
+        ea.w = buf[nx2];
+        prof_begin("edt2_y", s);
+        QAI_TRY(launch_env(1, false, ea, t, s));
         prof_end(s);
-    } else if (p.ny > 1) {
-        ea.write_words = p.keep_w2;
-        prof_begin("edt2_y_interp", s);
-        QAI_TRY(launch_env(1, true, ea, t, s));
-        prof_end(s);
-    } else {
-        InterpArgs ia = {p.w1, p.w2, p.xq, p.out, p.nx, eta_eb, p.power, p.taps.d2sq, p.taps.w};
-        prof_begin("interp", s);
-        QAI_TRY(launch_interp(ia, s));
-        prof_end(s);
+        c2 = nx2;
     }
+    if (p.nz > 1) {
+        const int nx2 = (c2 == o0) ? o1 : o0;
+        ea.win = buf[c2];
+        ea.w = buf[nx2];
+        prof_begin("edt2_z", s);
+        QAI_TRY(launch_env(2, false, ea, t, s));
+        prof_end(s);
+        c2 = nx2;
+    }
+
+    // step E
+    InterpArgs ia = {buf[w1], buf[c2], p.xq, p.out, p.nx * p.ny * p.nz, p.eta * p.eb, p.power, p.taps.d2sq, p.taps.w};
+    prof_begin("interp", s);
+    QAI_TRY(launch_interp(ia, s));
+    prof_end(s);
+    p.w1_final = buf[w1];
+    p.w2_final = buf[c2];
     return hipSuccess;
 }
 

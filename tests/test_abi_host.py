@@ -37,7 +37,7 @@ def test_workspace_bytes(lib):
     for shape in ((1, 1, 1), (64, 64, 64), (256, 384, 384), (1, 1800, 3600)):
         n = math.prod(shape)
         b = lib.qai_workspace_bytes(_lib.Dims(*shape))
-        words = 2 * (((n * 4) + 255) // 256) * 256
+        words = 3 * (((n * 4) + 255) // 256) * 256
         assert b == 64 * 1024 + words
     for bad in ((0, 4, 4), (4, -1, 4), (1, 1, 16385)):
         assert lib.qai_workspace_bytes(_lib.Dims(*bad)) == 0
@@ -63,6 +63,7 @@ def test_argument_errors_are_caught_on_the_host(lib):
         assert call_ex(lib, eb=eb) == -1, eb
     assert call_ex(lib, params=_lib.Params(float("nan"), 1.0, 0)) == -1
     assert call_ex(lib, params=_lib.Params(0.9, 0.0, 0)) == -1
+    assert call_ex(lib, params=_lib.Params(0.9, 1.0, 1)) == -1
     assert call_ex(lib, ws=None) == -3
     assert call_ex(lib, ws_bytes=100) == -3
     assert call_ex(lib, ws=ctypes.c_void_p(0x1010)) == -3  # misaligned
