@@ -153,6 +153,28 @@ int qai_batch_plan_launch_per_field(qai_batch_plan* plan, void* stream);
 
 void qai_batch_plan_destroy(qai_batch_plan* plan);
 
+/* ------------------------------------------------------------ tuning
+ * Launch geometry and per-pass algorithm choice (process-wide; the batched
+ * plan captures the setting current at its creation).  Results do not depend
+ * on it: every choice computes the same exact transforms. */
+typedef struct {
+    int32_t edt1_algo[2];  /* y and z passes of the first EDT: 0 streaming envelope, 1 windowed
+                              search over LDS tiles, 2 banded envelope over LDS tiles */
+    int32_t edt2_algo[2];  /* the same for the second EDT */
+    int32_t edt1_ring;     /* live-window ring entries of the streaming envelope: 16, 32 or 64 */
+    int32_t edt2_ring;
+    int32_t tile_log2[2];  /* log2 of x-columns per tile of the tiled variants, y and z (-1: auto) */
+    int32_t seed_rows;     /* x-lines (wavefronts) per workgroup of the seed passes (1..8) */
+    int32_t seed_planes;   /* z-planes marched per workgroup of the seed passes (>= 1) */
+    int32_t window_threads; /* threads per workgroup of the windowed variant (64..1024) */
+} qai_tuning;
+
+/* Copy the current setting into *t. */
+int qai_tuning_get(qai_tuning* t);
+/* Replace the current setting (validated; QAI_EINVAL if out of range).  NULL
+ * restores the built-in defaults. */
+int qai_tuning_set(const qai_tuning* t);
+
 /* ------------------------------------------------------------ utilities */
 
 /* Plain device copy of n 32-bit words (a bandwidth probe: the achievable HBM

@@ -177,6 +177,41 @@ def copy_probe(src, dst, stream=None):
                                     _stream_ptr(stream)))
 
 
+TUNING_FIELDS = ("edt1_algo", "edt2_algo", "edt1_ring", "edt2_ring", "tile_log2", "seed_rows", "seed_planes",
+                 "window_threads")
+
+
+def get_tuning():
+    """The current launch setting as a dict (see qai_tuning in include/qai.h)."""
+    t = _lib.Tuning()
+    _lib.check(lib().qai_tuning_get(ctypes.byref(t)))
+    out = {}
+    for k in TUNING_FIELDS:
+        v = getattr(t, k)
+        out[k] = list(v) if hasattr(v, "__len__") else int(v)
+    return out
+
+
+def set_tuning(cfg=None, **kw):
+    """Replace the launch setting; ``None`` restores the defaults.  Keys not
+    given keep their current values."""
+    if cfg is None and not kw:
+        _lib.check(lib().qai_tuning_set(None))
+        return get_tuning()
+    cur = get_tuning()
+    cur.update(cfg or {})
+    cur.update(kw)
+    t = _lib.Tuning()
+    for k in TUNING_FIELDS:
+        v = cur[k]
+        if isinstance(v, (list, tuple)):
+            getattr(t, k)[:] = [int(x) for x in v]
+        else:
+            setattr(t, k, int(v))
+    _lib.check(lib().qai_tuning_set(ctypes.byref(t)))
+    return get_tuning()
+
+
 def profile(on=True):
     _lib.check(lib().qai_profile_enable(1 if on else 0))
 

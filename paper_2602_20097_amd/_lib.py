@@ -35,12 +35,18 @@ class Taps(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("q", "b1", "sb", "s", "d1sq", "b2", "d2sq", "w")]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("edt1_algo", ctypes.c_int32 * 2), ("edt2_algo", ctypes.c_int32 * 2), ("edt1_ring", ctypes.c_int32),
+                ("edt2_ring", ctypes.c_int32), ("tile_log2", ctypes.c_int32 * 2), ("seed_rows", ctypes.c_int32),
+                ("seed_planes", ctypes.c_int32), ("window_threads", ctypes.c_int32)]
+
+
 Dims = ctypes.c_int64 * 3
 
 EXPORTS = ["qai_mitigate", "qai_workspace_bytes", "qai_mitigate_ex", "qai_backward", "qai_device_status",
            "qai_last_error", "qai_batch_workspace_bytes", "qai_batch_plan_create", "qai_batch_plan_launch",
            "qai_batch_plan_launch_per_field", "qai_batch_plan_destroy", "qai_copy_probe",
-           "qai_profile_enable", "qai_stage_times"]
+           "qai_profile_enable", "qai_stage_times", "qai_tuning_get", "qai_tuning_set"]
 
 _lib = None
 
@@ -74,6 +80,8 @@ def load(path=LIB_PATH):
     lib.qai_batch_plan_destroy.restype = None
     lib.qai_copy_probe.argtypes = [P, P, SZ, P]
     lib.qai_profile_enable.argtypes = [I]
+    lib.qai_tuning_get.argtypes = [ctypes.POINTER(Tuning)]
+    lib.qai_tuning_set.argtypes = [ctypes.POINTER(Tuning)]
     lib.qai_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_char_p), I,
                                     ctypes.POINTER(I), I]
     for name in EXPORTS:

@@ -80,6 +80,19 @@ struct StageRec {
     hipEvent_t a, b;
 };
 std::mutex g_prof_mu;
+std::mutex g_tune_mu;
+bool g_tune_set = false;
+qai::Tuning g_tune;
+
+qai::Tuning current_tuning()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_set) {
+        qai::default_tuning(g_tune);
+        g_tune_set = true;
+    }
+    return g_tune;
+}
 bool g_prof_on = false;
 std::vector<StageRec> g_pending;
 std::vector<std::pair<const char*, double>> g_acc;
@@ -172,8 +185,7 @@ int plain_checked(const float* field, const int64_t dims[3], float eb, const qai
     pl.bufC = word_buffer(ws, n, 2);
     if (taps)
         pl.taps = *taps;
-    qai::Tuning t;
-    qai::default_tuning(t);
+    const qai::Tuning t = current_tuning();
     e = qai::run_plain(pl, t, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail_hip(e, "kernel launch");
@@ -306,6 +318,62 @@ int qai_copy_probe(const void* src, void* dst, size_t n_words, void* stream)
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? QAI_OK : fail_hip(e, "copy launch");
+}
+
+int qai_tuning_get(qai_tuning* out)
+{
+    g_err.clear();
+    if (!out)
+        return fail(QAI_EINVAL, "tuning pointer is NULL");
+    const qai::Tuning t = current_tuning();
+    out->edt1_algo[0] = t.edt1_algo[1];
+    out->edt1_algo[1] = t.edt1_algo[2];
+    out->edt2_algo[0] = t.env_algo[1];
+    out->edt2_algo[1] = t.env_algo[2];
+    out->edt1_ring = t.edt1_cap[1];
+    out->edt2_ring = t.stream_cap[1];
+    out->tile_log2[0] = t.env_tx_log2[1];
+    out->tile_log2[1] = t.env_tx_log2[2];
+    out->seed_rows = t.seed_ty;
+    out->seed_planes = t.seed_tz;
+    out->window_threads = t.env_threads;
+    return QAI_OK;
+}
+
+int qai_tuning_set(const qai_tuning* in)
+{
+    g_err.clear();
+    qai::Tuning t;
+    qai::default_tuning(t);
+    if (in) {
+        for (int k = 0; k < 2; ++k) {
+            if (in->edt1_algo[k] < 0 || in->edt1_algo[k] > 2 || in->edt2_algo[k] < 0 || in->edt2_algo[k] > 2)
+                return fail(QAI_EINVAL, "algorithm choice must be 0, 1 or 2");
+            if (in->tile_log2[k] < -1 || in->tile_log2[k] > 6)
+                return fail(QAI_EINVAL, "tile_log2 must be in [-1, 6]");
+        }
+        for (int r : {in->edt1_ring, in->edt2_ring})
+            if (r != 16 && r != 32 && r != 64)
+                return fail(QAI_EINVAL, "ring sizes must be 16, 32 or 64");
+        if (in->seed_rows < 1 || in->seed_rows > 8 || in->seed_planes < 1 || in->seed_planes > 4096)
+            return fail(QAI_EINVAL, "seed_rows must be in [1, 8] and seed_planes >= 1");
+        if (in->window_threads < 64 || in->window_threads > 1024 || in->window_threads % 64)
+            return fail(QAI_EINVAL, "window_threads must be a multiple of 64 in [64, 1024]");
+        for (int a = 1; a <= 2; ++a) {
+            t.edt1_algo[a] = in->edt1_algo[a - 1];
+            t.env_algo[a] = in->edt2_algo[a - 1];
+            t.edt1_cap[a] = in->edt1_ring;
+            t.stream_cap[a] = in->edt2_ring;
+            t.env_tx_log2[a] = in->tile_log2[a - 1];
+        }
+        t.seed_ty = in->seed_rows;
+        t.seed_tz = in->seed_planes;
+        t.env_threads = in->window_threads;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune = t;
+    g_tune_set = true;
+    return QAI_OK;
 }
 
 int qai_profile_enable(int on)

@@ -218,7 +218,7 @@ __device__ __forceinline__ int slab_key(const SeedArgs& a, int64_t i, bool& bad)
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_seed_slab(SlabArgs A)
+__global__ __launch_bounds__(512) void k_seed_slab(SlabArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const SeedArgs& a = A.s;
@@ -759,11 +759,42 @@ __global__ __launch_bounds__(128) void k_env_stream(EnvArgs a)
         const uint32_t* __restrict__ inp = a.win + tb;
         uint32_t* __restrict__ outp = a.w + tb;
 
+        // live window [lo, top] of Algorithm 1's stack in the ring (logical
+        // indices; slot = index mod C); only these scalars cross rows
         int lo = 0, top = -1;
-        uint32_t wtop = 0, wsec = 0, wlo = 0, wlo1 = 0;
-        int htop = 0, hsec = 0, hlo = 0, hlo1 = 0;
         bool ovf = !valid;
-        int e = 0; // next row to emit (uniform within the lane's group)
+        int e = 0;                       // next row to emit (uniform within the lane's group)
+        uint32_t bestB = QAI_WORD_INF;   // value at row e over the sites seen so far
+        uint32_t bestW = QAI_WORD_INF;   // the corresponding word (value and sign code)
+        uint32_t* const rwl = rw + lane;
+        uint16_t* const rhl = rh + lane;
+#define RW(k) rwl[((k) & (C - 1)) * 64]
+#define RH(k) ((int)rhl[((k) & (C - 1)) * 64])
+
+        // owner of row r among the live entries (the pointer only moves forward)
+        auto refresh = [&](int r) {
+            if (top < lo) {
+                bestB = QAI_WORD_INF;
+                bestW = QAI_WORD_INF;
+                return;
+            }
+            uint32_t wl = RW(lo);
+            int hl = RH(lo);
+            uint32_t bl = (wl >> 2) + sq24(r - hl);
+            for (int it = 0; it < C && lo < top; ++it) {
+                const uint32_t wn = RW(lo + 1);
+                const int hn = RH(lo + 1);
+                const uint32_t bn = (wn >> 2) + sq24(r - hn);
+                if (!(bn < bl))
+                    break;
+                ++lo;
+                wl = wn;
+                hl = hn;
+                bl = bn;
+            }
+            bestB = bl;
+            bestW = wl + (sq24(r - hl) << 2);
+        };
 
         uint32_t cur[8], nxt[8];
 #pragma unroll
@@ -781,68 +812,40 @@ __global__ __launch_bounds__(128) void k_env_stream(EnvArgs a)
                 const uint32_t w = cur[k];
                 if (w != QAI_WORD_INF && !ovf) {
                     const uint32_t g = w >> 2;
-                    for (int it = 0; it < C && top > lo; ++it) {
-                        if (!remove_sel<SMALL>(wsec >> 2, wtop >> 2, g, hsec, htop, i))
-                            break;
-                        --top;
-                        wtop = wsec;
-                        htop = hsec;
-                        if (top > lo) {
-                            const int sl = ((top - 1) & (C - 1)) * 64 + lane;
-                            wsec = rw[sl];
-                            hsec = rh[sl];
+                    if (top > lo) {
+                        uint32_t wt = RW(top);
+                        int ht = RH(top);
+                        for (int it = 0; it < C && top > lo; ++it) {
+                            const uint32_t ws = RW(top - 1);
+                            const int hs = RH(top - 1);
+                            if (!remove_sel<SMALL>(ws >> 2, wt >> 2, g, hs, ht, i))
+                                break;
+                            --top;
+                            wt = ws;
+                            ht = hs;
                         }
                     }
                     if (top - lo + 1 >= C) {
                         ovf = true;
                     } else {
                         ++top;
-                        const int sl = (top & (C - 1)) * 64 + lane;
-                        rw[sl] = w;
-                        rh[sl] = (uint16_t)i;
-                        wsec = wtop;
-                        hsec = htop;
-                        wtop = w;
-                        htop = i;
-                        if (top == lo) {
-                            wlo = w;
-                            hlo = i;
-                        } else if (top == lo + 1) {
-                            wlo1 = w;
-                            hlo1 = i;
-                        }
+                        RW(top) = w;
+                        rhl[(top & (C - 1)) * 64] = (uint16_t)i;
+                        if (e <= i)
+                            refresh(e);
                     }
                 }
+                // emit the rows that are final for every column of the group
                 for (int guard = 0; guard <= n; ++guard) {
-                    bool ok = false;
-                    uint32_t word = QAI_WORD_INF;
-                    if (e <= i) {
-                        if (ovf) {
-                            ok = true;
-                        } else if (top >= lo) {
-                            for (int it = 0; it < C && lo < top; ++it) {
-                                if (!((wlo1 >> 2) + sq24(e - hlo1) < (wlo >> 2) + sq24(e - hlo)))
-                                    break;
-                                ++lo;
-                                wlo = wlo1;
-                                hlo = hlo1;
-                                if (lo < top) {
-                                    const int sl = ((lo + 1) & (C - 1)) * 64 + lane;
-                                    wlo1 = rw[sl];
-                                    hlo1 = rh[sl];
-                                }
-                            }
-                            const uint32_t d2 = sq24(e - hlo);
-                            ok = (wlo >> 2) + d2 <= sq24(i + 1 - e);
-                            word = wlo + (d2 << 2);
-                        }
-                    }
+                    const bool ok = (e <= i) && (ovf || bestB <= sq24(i + 1 - e));
                     const bool emit = (__ballot(ok) & gmask) == gmask;
                     if (__ballot(emit) == 0ull)
                         break;
                     if (emit) {
-                        if (!ovf)
-                            outp[(int64_t)e * stride + lane] = word;
+                        if (!ovf) {
+                            outp[(int64_t)e * stride + lane] = bestW;
+                            refresh(e + 1);
+                        }
                         ++e;
                     }
                 }
@@ -854,25 +857,12 @@ __global__ __launch_bounds__(128) void k_env_stream(EnvArgs a)
         // every remaining row is final
         for (; e < n; ++e) {
             if (!ovf) {
-                uint32_t word = QAI_WORD_INF;
-                if (top >= lo) {
-                    for (int it = 0; it < C && lo < top; ++it) {
-                        if (!((wlo1 >> 2) + sq24(e - hlo1) < (wlo >> 2) + sq24(e - hlo)))
-                            break;
-                        ++lo;
-                        wlo = wlo1;
-                        hlo = hlo1;
-                        if (lo < top) {
-                            const int sl = ((lo + 1) & (C - 1)) * 64 + lane;
-                            wlo1 = rw[sl];
-                            hlo1 = rh[sl];
-                        }
-                    }
-                    word = wlo + (sq24(e - hlo) << 2);
-                }
-                outp[(int64_t)e * stride + lane] = word;
+                outp[(int64_t)e * stride + lane] = bestW;
+                refresh(e + 1);
             }
         }
+#undef RW
+#undef RH
 
         // columns whose live window outgrew the ring: exact outward search,
         // one column at a time by the whole wave, staged in the ring's LDS
