@@ -907,6 +907,206 @@ __global__ __launch_bounds__(128) void k_env_stream(EnvArgs a)
     }
 }
 
+// Per-lane online envelope for payload-free words (the second EDT).  Same
+// sweep as k_env_stream, but each lane emits its own rows: a row is final as
+// soon as no later site can undercut it (its best value is at most the squared
+// distance to the next unread row).  One emission attempt per row keeps the
+// memory operations per row fixed (a lane with nothing final repeats its last
+// store, so the compiler's counter waits stay exact); after every 8 rows, lanes
+// whose live window nears the ring size emit all their final rows.  Ring
+// entries are packed (g << hb) | row, checked on the host to fit 32 bits.
+// Spare lanes of a partial tile shadow lane 0 (same column, same stores).
+template <int AXIS, int C, bool SMALL, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_env_lane(EnvArgs a, int hb)
+{
+    __shared__ uint32_t ring[WPB * C * 64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint32_t* const rl = ring + wv * C * 64 + lane;
+    const int n = (int)((AXIS == 1) ? a.ny : a.nz);
+    const int64_t stride = (AXIS == 1) ? a.nx : a.nx * a.ny;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    const uint32_t hm = (1u << hb) - 1u;
+    const uint64_t ngroups = (a.ntiles + WPB - 1) / WPB;
+#define SLOT(k) (((k) & (C - 1)) * 64)
+
+    for (uint64_t t = blockIdx.x; t < ngroups; t += gridDim.x) {
+        const uint64_t tile = xcd_remap(t, ngroups) * WPB + wv;
+        if (tile >= a.ntiles)
+            continue;
+        const int64_t xb = (int64_t)(tile % (uint64_t)nxb), o = (int64_t)(tile / (uint64_t)nxb);
+        const int64_t x0 = xb * 64;
+        const bool valid = x0 + lane < a.nx;
+        const int64_t tb = ((AXIS == 1) ? o * a.nx * a.ny : o * a.nx) + x0;
+        const uint32_t* __restrict__ inb = a.win + tb;
+        uint32_t* const outb = a.w + tb;
+        const uint32_t us = (uint32_t)stride;
+        const uint32_t uc = valid ? (uint32_t)lane : 0u;
+
+        int lo = 0, top = -1, e = 0;
+        uint32_t be = 0xFFFFFFFFu;          // value at row e over the sites read so far
+        uint32_t f0g = 0, f1g = 0, t0g = 0, t1g = 0, f2p = 0, t2p = 0;
+        int f0h = 0, f1h = 0, t0h = 0, t1h = 0;
+        bool ovf = false;
+        uint32_t prow = 0, pval = QAI_WORD_INF;
+
+        // advance the owner of row r (entries only leave from the front)
+        auto front_to = [&](int r) {
+            if (top < lo)
+                return;
+            uint32_t a0 = f0g + sq24(r - f0h);
+            if (lo < top) {
+                uint32_t a1 = f1g + sq24(r - f1h);
+                if (a1 < a0) {
+                    ++lo;
+                    f0g = f1g; f0h = f1h; a0 = a1;
+                    f1g = f2p >> hb; f1h = (int)(f2p & hm);
+                    f2p = rl[SLOT(lo + 2)];
+#pragma unroll 1
+                    for (int it = 0; it < C && lo < top; ++it) {
+                        a1 = f1g + sq24(r - f1h);
+                        if (!(a1 < a0))
+                            break;
+                        ++lo;
+                        f0g = f1g; f0h = f1h; a0 = a1;
+                        f1g = f2p >> hb; f1h = (int)(f2p & hm);
+                        f2p = rl[SLOT(lo + 2)];
+                    }
+                }
+            }
+            be = a0;
+        };
+
+        auto row_step = [&](int i, uint32_t w) {
+            if (w != QAI_WORD_INF && !ovf) {
+                const uint32_t g = w >> 2;
+                if (top > lo && remove_sel<SMALL>(t1g, t0g, g, t1h, t0h, i)) {
+                    --top;
+                    t0g = t1g; t0h = t1h;
+                    t1g = t2p >> hb; t1h = (int)(t2p & hm);
+                    t2p = rl[SLOT(top - 2)];
+#pragma unroll 1
+                    for (int it = 0; it < C && top > lo; ++it) {
+                        if (!remove_sel<SMALL>(t1g, t0g, g, t1h, t0h, i))
+                            break;
+                        --top;
+                        t0g = t1g; t0h = t1h;
+                        t1g = t2p >> hb; t1h = (int)(t2p & hm);
+                        t2p = rl[SLOT(top - 2)];
+                    }
+                }
+                if (top - lo + 1 >= C) {
+                    ovf = true;
+                } else {
+                    ++top;
+                    const uint32_t pk = (g << hb) | (uint32_t)i;
+                    rl[SLOT(top)] = pk;
+                    t2p = (t1g << hb) | (uint32_t)t1h;
+                    t1g = t0g; t1h = t0h; t0g = g; t0h = i;
+                    const uint32_t vi = g + sq24(e - i);
+                    if (top == lo) {
+                        f0g = g; f0h = i; be = vi;
+                    } else {
+                        if (top == lo + 1) { f1g = g; f1h = i; }
+                        if (top == lo + 2) f2p = pk;
+                        be = min(be, vi);
+                    }
+                }
+            }
+            const bool fin = !ovf && e <= i && top >= lo && be <= sq24(i + 1 - e);
+            const uint32_t row = fin ? (uint32_t)e : prow;
+            const uint32_t val = fin ? (be << 2) : pval;
+            outb[row * us + uc] = val;
+            prow = row;
+            pval = val;
+            e += fin ? 1 : 0;
+            if (fin)
+                front_to(e);
+        };
+
+        auto catch_up = [&](int i) {
+#pragma unroll 1
+            for (int it = 0; it < n; ++it) {
+                const bool fin = !ovf && top - lo + 1 > C - 9 && e <= i && be <= sq24(i + 1 - e);
+                if (__ballot(fin) == 0ull)
+                    break;
+                if (fin) {
+                    outb[(uint32_t)e * us + uc] = be << 2;
+                    ++e;
+                    front_to(e);
+                }
+            }
+        };
+
+        uint32_t A[8], B[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            A[k] = inb[(uint32_t)min(k, n - 1) * us + uc];
+        for (int i0 = 0; i0 < n; i0 += 16) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                B[k] = inb[(uint32_t)min(i0 + 8 + k, n - 1) * us + uc];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (i0 + k < n)
+                    row_step(i0 + k, A[k]);
+            catch_up(min(i0 + 7, n - 1));
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                A[k] = inb[(uint32_t)min(i0 + 16 + k, n - 1) * us + uc];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (i0 + 8 + k < n)
+                    row_step(i0 + 8 + k, B[k]);
+            catch_up(min(i0 + 15, n - 1));
+        }
+        // every row left is final
+#pragma unroll 1
+        for (int it = 0; it < n; ++it) {
+            const bool more = !ovf && e < n;
+            if (__ballot(more) == 0ull)
+                break;
+            if (more) {
+                outb[(uint32_t)e * us + uc] = (top >= lo) ? (be << 2) : QAI_WORD_INF;
+                ++e;
+                if (e < n)
+                    front_to(e);
+            }
+        }
+#undef SLOT
+
+        // columns whose live window outgrew the ring: exact outward search,
+        // one column at a time by the whole wave
+        uint64_t om = __ballot(ovf && valid);
+        while (om) {
+            const int l = __ffsll((unsigned long long)om) - 1;
+            om &= om - 1ull;
+            for (int p = lane; p < n; p += 64) {
+                uint32_t best = inb[(int64_t)p * stride + l];
+                for (int r = 1; r < n; ++r) {
+                    const uint32_t r2 = (uint32_t)r * (uint32_t)r << 2;
+                    if (r2 > (best | 3u))
+                        break;
+                    const int l0 = p - r, h0 = p + r;
+                    if (l0 < 0 && h0 >= n)
+                        break;
+                    if (l0 >= 0) {
+                        const uint32_t cand = word_add(inb[(int64_t)l0 * stride + l], r2);
+                        if ((cand >> 2) <= (best >> 2))
+                            best = cand;
+                    }
+                    if (h0 < n) {
+                        const uint32_t cand = word_add(inb[(int64_t)h0 * stride + l], r2);
+                        if ((cand >> 2) < (best >> 2))
+                            best = cand;
+                    }
+                }
+                outb[(int64_t)p * stride + l] = best;
+            }
+        }
+    }
+}
+
 __global__ void k_clear(uint32_t* p, int n)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -927,7 +1127,7 @@ void default_tuning(Tuning& t)
 {
     for (int i = 0; i < 3; ++i) {
         t.env_tx_log2[i] = -1;
-        t.env_algo[i] = 0;
+        t.env_algo[i] = 3;
         t.edt1_algo[i] = 1;
         t.stream_cap[i] = 32;
         t.edt1_cap[i] = 16;
@@ -1089,6 +1289,34 @@ static hipError_t launch_stream_t(EnvArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Ring entries pack (g << hb) | row into 32 bits: hb covers the rows of the
+// pass, g the largest squared distance the previous passes can produce.
+static bool lane_geometry(int axis, const EnvArgs& a, int& hb, bool& small)
+{
+    const int64_t n = axis == 1 ? a.ny : a.nz;
+    const int64_t gmax = (a.nx - 1) * (a.nx - 1) + (axis == 2 ? (a.ny - 1) * (a.ny - 1) : 0);
+    hb = 1;
+    while (((int64_t)1 << hb) < n)
+        ++hb;
+    small = n < 4096 && gmax < (1 << 24) && n * gmax + n * n * n / 4 < (int64_t)1 << 31;
+    return n < 65536 && hb < 32 && gmax < ((int64_t)1 << (32 - hb));
+}
+
+template <int AXIS>
+static hipError_t launch_lane_t(EnvArgs a, int hb, bool small, hipStream_t s)
+{
+    constexpr int WPB = 4;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    a.ntiles = (uint64_t)(nxb * (AXIS == 1 ? a.nz : a.ny));
+    const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
+    const dim3 grid(grid_cap(groups, 1u << 20)), blk(64 * WPB);
+    if (small)
+        hipLaunchKernelGGL((k_env_lane<AXIS, 32, true, WPB>), grid, blk, 0, s, a, hb);
+    else
+        hipLaunchKernelGGL((k_env_lane<AXIS, 32, false, WPB>), grid, blk, 0, s, a, hb);
+    return hipGetLastError();
+}
+
 hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_t s)
 {
     const int64_t n = axis == 1 ? a.ny : a.nz;
@@ -1113,6 +1341,12 @@ hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_
     }
     if (t.env_algo[axis] == 2 && n <= 64 * 32)
         return launch_band2(axis, epi, a, t, s);
+    if (t.env_algo[axis] == 3 && !epi) {
+        int hb;
+        bool small;
+        if (lane_geometry(axis, a, hb, small))
+            return axis == 1 ? launch_lane_t<1>(a, hb, small, s) : launch_lane_t<2>(a, hb, small, s);
+    }
     if (epi)
         return hipErrorInvalidValue; // the streaming pass never carries step E
     const int cap = t.stream_cap[axis] <= 16 ? 16 : (t.stream_cap[axis] <= 32 ? 32 : 64);

@@ -154,3 +154,26 @@ def test_headline_512_full_parity():
     g, r = assert_parity(xq, eb, label="grf512")
     # the relaxed bound of Section VII-C on the whole field
     assert np.abs(g["out"].astype(np.float64) - x32).max() <= (1 + 0.9) * eb * (1 + 1e-6)
+
+
+def test_every_pass_algorithm_gives_the_same_transform():
+    """Each per-pass algorithm choice (qai_tuning) computes the same exact EDTs."""
+    import paper_2602_20097_amd as qai
+    cases = [synth.make_workload("grf64_k3_eb1e-2")[1:4:2]]
+    for shape in ((5, 70, 130), (33, 33, 33), (3, 65, 200), (2, 300, 77)):
+        x32, xq, q, eb = synth.quantize(synth.grf(shape, 3.0, 5 + sum(shape)), 2e-2)
+        cases.append((xq, eb))
+    base = qai.get_tuning()
+    try:
+        for xq, eb in cases:
+            r = oracle.qai(xq, eb)
+            for a1 in (0, 1, 2):
+                for a2 in (0, 1, 2, 3):
+                    qai.set_tuning(edt1_algo=[a1, a1], edt2_algo=[a2, a2])
+                    print(f"tuning edt1 {a1} edt2 {a2} shape {xq.shape}", flush=True)
+                    g = gpu_run(xq, eb)
+                    for k in KEYS:
+                        assert np.array_equal(g[k].astype(np.int64), r[k].astype(np.int64)), (k, a1, a2, xq.shape)
+    finally:
+        qai.set_tuning(None)
+    assert qai.get_tuning() == base
