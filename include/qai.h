@@ -166,7 +166,9 @@ typedef struct {
     int32_t edt1_ring;     /* live-window ring entries of the streaming envelope: 16, 32 or 64 */
     int32_t edt2_ring;
     int32_t tile_log2[2];  /* log2 of x-columns per tile of the tiled variants, y and z (-1: auto) */
-    int32_t seed_rows;     /* x-lines (wavefronts) per workgroup of the seed passes (1..8) */
+    int32_t seed_rows;     /* x-lines (wavefronts) per workgroup of the LDS-slab seed passes
+                              (1..8); 0 selects the register-resident variant (8 lines per
+                              workgroup) wherever x-lines hold at most 512 voxels */
     int32_t seed_planes;   /* z-planes marched per workgroup of the seed passes (>= 1) */
     int32_t window_threads; /* threads per workgroup of the windowed variant (64..1024) */
 } qai_tuning;

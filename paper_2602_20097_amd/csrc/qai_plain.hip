@@ -369,6 +369,230 @@ __global__ __launch_bounds__(512) void k_seed_slab(SlabArgs A)
     }
 }
 
+__device__ __forceinline__ int32_t raw_word_d1(const uint32_t* w1, int64_t i)
+{
+    const uint32_t w = w1[i];
+    return (w == QAI_WORD_INF) ? -1 : (int32_t)word_d2(w);
+}
+
+// Register-resident variant of the seed passes for lines of up to NCH * 64
+// voxels.  A workgroup of WPB wavefronts owns WPB adjacent x-lines (one per
+// wave) and marches them through tz planes.  Each wave keeps its own line of
+// planes z-1, z, z+1 in registers (the +-z neighbours), the current plane's
+// lines of the group and its two halo lines sit in LDS (the +-x, +-y
+// neighbours; double-buffered, one barrier per plane), and the site masks of
+// the x-scan stay in scalar registers.
+template <int MODE>
+__device__ __forceinline__ int reg_key(uint32_t raw, float inv2eb, float two_eb, bool& bad)
+{
+    if (MODE == 0)
+        return recover_q(__uint_as_float(raw), inv2eb, two_eb, bad);
+    const int sgn = word_sign(raw);
+    const int b1 = (raw != QAI_WORD_INF && word_d2(raw) == 0u) ? 4 : 0;
+    return (sgn & 3) | b1;
+}
+
+template <int MODE, int NCH, int WPB, bool TAPS>
+__global__ __launch_bounds__(64 * WPB) void k_seed_reg(SlabArgs A)
+{
+    constexpr int W = NCH * 64;          // LDS line pitch
+    constexpr int R = WPB + 2;           // lines per LDS plane (with the two halo lines)
+    __shared__ int rows[2][R * W];
+    const SeedArgs& a = A.s;
+    const int nx = (int)a.nx;
+    const int64_t ny = a.ny, nz = a.nz;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const bool hy = ny > 1, hz = nz > 1, hx = nx > 1;
+    const uint32_t* __restrict__ src = (MODE == 0) ? (const uint32_t*)a.xq : a.w1;
+    const uint64_t below = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const uint64_t above = ~0ull << lane;
+    const uint64_t nblocks = (uint64_t)(A.nby * A.nbz);
+    bool bad = false;
+
+    for (uint64_t t = blockIdx.x; t < nblocks; t += gridDim.x) {
+        const uint64_t bl = xcd_remap(t, nblocks);
+        const int64_t by = (int64_t)(bl % (uint64_t)A.nby), bz = (int64_t)(bl / (uint64_t)A.nby);
+        const int64_t y0 = by * WPB, z0 = bz * A.tz;
+        const int64_t z1 = min(nz, z0 + A.tz);
+        const int64_t y = y0 + wave;
+        // the halo lines are read by the first and last wave
+        const int64_t yh = (wave == 0) ? y0 - 1 : y0 + WPB;
+        const bool halo = hy && (wave == 0 || wave == WPB - 1);
+        const int hrow = (wave == 0) ? 0 : R - 1;
+
+        auto load = [&](int64_t zz, int64_t yy, uint32_t (&r)[NCH]) {
+            if (zz >= 0 && zz < nz && yy >= 0 && yy < ny) {
+                const uint32_t* p = src + (zz * ny + yy) * (int64_t)nx;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int x = c * 64 + lane;
+                    r[c] = (c + 1 < NCH || x < nx) ? p[x] : 0u;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+                    r[c] = 0u;
+            }
+        };
+        auto keys = [&](const uint32_t (&r)[NCH], int (&k)[NCH]) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                k[c] = reg_key<MODE>(r[c], a.inv2eb, a.two_eb, bad);
+        };
+        auto put = [&](int b, int row, const int (&k)[NCH]) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                rows[b][row * W + c * 64 + lane] = k[c];
+        };
+
+        uint32_t raw[NCH], hraw[NCH];
+        int P0[NCH], P1[NCH], P2[NCH];
+        load(z0 - 1, y, raw);
+        keys(raw, P0);
+        load(z0, y, raw);
+        keys(raw, P1);
+        if (halo)
+            load(z0, yh, hraw);
+        load(z0 + 1, y, raw);
+        keys(raw, P2);
+        __syncthreads();
+        put(0, wave + 1, P1);
+        if (halo) {
+            int H[NCH];
+            keys(hraw, H);
+            put(0, hrow, H);
+        }
+        load(z0 + 2, y, raw);
+        if (halo)
+            load(z0 + 1, yh, hraw);
+        __syncthreads();
+
+        int cur = 0;
+        for (int64_t z = z0; z < z1; ++z) {
+            if (y < ny) {
+                const int* rc = &rows[cur][(wave + 1) * W];
+                const int* rym = hy ? rc - W : rc;
+                const int* ryp = hy ? rc + W : rc;
+                const bool line_in = (!hy || (y >= 1 && y <= ny - 2)) && (!hz || (z >= 1 && z <= nz - 2));
+                // sweep 1 (right to left): stencil, site mask, and per lane the
+                // nearest site at or after it (distance <= 1023 or none) with its
+                // code, plus the highest site at or below it inside the chunk;
+                // packed: dr | codeR << 10 | (bl + 1) << 12 | codeL << 19
+                uint32_t pk[NCH];
+                uint32_t lastp[NCH]; // per chunk: (highest site + 1) | its code << 16, 0 if none
+                int first = -1, fc = 0;
+#pragma unroll
+                for (int c = NCH - 1; c >= 0; --c) {
+                    const int x = c * 64 + lane;
+                    const int kc = P1[c];
+                    const int kxp = hx ? rc[min(x + 1, W - 1)] : kc;
+                    const int kxm = hx ? rc[max(x - 1, 0)] : kc;
+                    const int kyp = ryp[x], kym = rym[x];
+                    const int kzp = hz ? P2[c] : kc, kzm = hz ? P0[c] : kc;
+                    const bool in = line_in && (c + 1 < NCH || x < nx) && (!hx || (x >= 1 && x <= nx - 2));
+                    bool site;
+                    int sgn = 0;
+                    if (MODE == 0) {
+                        // Algorithm 2 (see k_seed_slab)
+                        int f = (kxp != kc) ? kxp - kc : ((kxm != kc) ? kxm - kc : 0);
+                        if (f == 0)
+                            f = (kyp != kc) ? kyp - kc : ((kym != kc) ? kym - kc : 0);
+                        if (f == 0)
+                            f = (kzp != kc) ? kzp - kc : ((kzm != kc) ? kzm - kc : 0);
+                        const bool steep =
+                            abs(kxp - kxm) >= 2 || abs(kyp - kym) >= 2 || abs(kzp - kzm) >= 2;
+                        site = in && f != 0;
+                        sgn = (site && !steep) ? (f > 0 ? 1 : -1) : 0;
+                    } else {
+                        const int sc = kc & 3;
+                        site = in && !(kc & 4) &&
+                               (((kxp & 3) != sc) || ((kxm & 3) != sc) || ((kyp & 3) != sc) || ((kym & 3) != sc) ||
+                                ((kzp & 3) != sc) || ((kzm & 3) != sc));
+                    }
+                    const uint64_t m = __ballot(site);
+                    const int code = (int)sign_code(sgn);
+                    if (TAPS && x < nx) {
+                        const int64_t i = (z * ny + y) * (int64_t)nx + x;
+                        if (MODE == 0) {
+                            if (a.tq) a.tq[i] = kc;
+                            if (a.tb1) a.tb1[i] = site ? 1 : 0;
+                            if (a.tsb) a.tsb[i] = (int8_t)sgn;
+                        } else {
+                            if (a.ts) a.ts[i] = (int8_t)((kc & 3) == 1 ? 1 : ((kc & 3) == 3 ? -1 : 0));
+                            if (a.td1) a.td1[i] = raw_word_d1(a.w1, i);
+                            if (a.tb2) a.tb2[i] = site ? 1 : 0;
+                        }
+                    }
+                    const uint64_t ml = m & below, mr = m & above;
+                    const int bl = ml ? 63 - __clzll(ml) : -1;
+                    const int br = mr ? __ffsll((unsigned long long)mr) - 1 : -1;
+                    // every lane takes part in the shuffles (source lanes must be active)
+                    const int cl = (MODE == 0) ? __shfl(code, bl & 63) : 0;
+                    const int cr = (MODE == 0) ? __shfl(code, br & 63) : 0;
+                    const int R = br >= 0 ? c * 64 + br : first;
+                    const int dr = R >= 0 ? R - x : 1023;
+                    const int crr = br >= 0 ? cr : fc;
+                    pk[c] = (uint32_t)dr | ((uint32_t)crr << 10) | ((uint32_t)(bl + 1) << 12) | ((uint32_t)cl << 19);
+                    lastp[c] = 0u;
+                    if (m) {
+                        const int hb = 63 - __clzll(m), lb = __ffsll((unsigned long long)m) - 1;
+                        lastp[c] = (uint32_t)(c * 64 + hb + 1) | ((uint32_t)((MODE == 0) ? __shfl(code, hb) : 0) << 16);
+                        first = c * 64 + lb;
+                        if (MODE == 0)
+                            fc = __shfl(code, lb);
+                    }
+                }
+                // sweep 2 (left to right): nearest of the two, ties to the left site
+                uint32_t* const wrow = a.wout + (z * ny + y) * (int64_t)nx;
+                uint32_t carry = 0u; // (last site before the chunk + 1) | code << 16
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int x = c * 64 + lane;
+                    const uint32_t v = pk[c];
+                    const int dr = (int)(v & 1023u);
+                    const int bl = (int)((v >> 12) & 127u) - 1;
+                    const int L = bl >= 0 ? c * 64 + bl : (int)(carry & 0xFFFFu) - 1;
+                    const int dl = L >= 0 ? x - L : 1023;
+                    uint32_t word = QAI_WORD_INF;
+                    if (dl < 1023 || dr < 1023) {
+                        const bool left = dl <= dr;
+                        const uint32_t d = (uint32_t)(left ? dl : dr);
+                        const uint32_t cd =
+                            left ? (bl >= 0 ? ((v >> 19) & 3u) : (carry >> 16)) : ((v >> 10) & 3u);
+                        word = word_make(d * d, (MODE == 0) ? cd : 0u);
+                    }
+                    if (c + 1 < NCH || x < nx)
+                        wrow[x] = word;
+                    if (lastp[c])
+                        carry = lastp[c];
+                }
+            }
+            if (z + 1 < z1) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    P0[c] = P1[c];
+                    P1[c] = P2[c];
+                }
+                keys(raw, P2);
+                put(cur ^ 1, wave + 1, P1);
+                if (halo) {
+                    int H[NCH];
+                    keys(hraw, H);
+                    put(cur ^ 1, hrow, H);
+                }
+                load(z + 3, y, raw);
+                if (halo)
+                    load(z + 2, yh, hraw);
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+    if (MODE == 0 && __ballot(bad) && (threadIdx.x & 63) == 0)
+        atomicOr(a.status, QAI_STATUS_QRANGE);
+}
+
 // ---------------------------------------------------------- interpolation
 // Step E for one voxel: C = w * S * eta * eb, out = x' + C (x' copied as is
 // where S = 0).
@@ -1133,7 +1357,7 @@ void default_tuning(Tuning& t)
         t.edt1_cap[i] = 16;
     }
     t.env_threads = 256;
-    t.seed_ty = 4;
+    t.seed_ty = 0;
     t.seed_tz = 16;
 }
 
@@ -1164,8 +1388,48 @@ static size_t slab_bytes(int64_t nx, int ty, int rows, int planes)
     return ring + (size_t)ty * nch * (64 + 8 + 4) + 64;
 }
 
+template <int MODE, int NCH>
+static hipError_t launch_seed_reg_t(const SeedArgs& in, int tz, hipStream_t s)
+{
+    const bool taps = (MODE == 0) ? (in.tq || in.tb1 || in.tsb) : (in.ts || in.td1 || in.tb2);
+    constexpr int WPB = 8;
+    SlabArgs A;
+    A.s = in;
+    A.ty = WPB;
+    A.rows = WPB + 2;
+    A.planes = 3;
+    A.tz = tz;
+    A.nby = (in.ny + WPB - 1) / WPB;
+    A.nbz = (in.nz + tz - 1) / tz;
+    const uint32_t grid = grid_cap((uint64_t)(A.nby * A.nbz), 1u << 20);
+    if (taps)
+        hipLaunchKernelGGL((k_seed_reg<MODE, NCH, WPB, true>), dim3(grid), dim3(64 * WPB), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_seed_reg<MODE, NCH, WPB, false>), dim3(grid), dim3(64 * WPB), 0, s, A);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_seed_reg(const SeedArgs& in, int tz, hipStream_t s)
+{
+    switch ((int)((in.nx + 63) / 64)) {
+    case 1: return launch_seed_reg_t<MODE, 1>(in, tz, s);
+    case 2: return launch_seed_reg_t<MODE, 2>(in, tz, s);
+    case 3: return launch_seed_reg_t<MODE, 3>(in, tz, s);
+    case 4: return launch_seed_reg_t<MODE, 4>(in, tz, s);
+    case 5: return launch_seed_reg_t<MODE, 5>(in, tz, s);
+    case 6: return launch_seed_reg_t<MODE, 6>(in, tz, s);
+    case 7: return launch_seed_reg_t<MODE, 7>(in, tz, s);
+    default: return launch_seed_reg_t<MODE, 8>(in, tz, s);
+    }
+}
+
 hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s, int want_ty, int want_tz)
 {
+    if (in.nx <= 512 && want_ty <= 0) {
+        const int tz = in.nz > 1 ? (want_tz > 0 ? want_tz : 16) : 1;
+        return mode == 0 ? launch_seed_reg<0>(in, tz, s) : launch_seed_reg<1>(in, tz, s);
+    }
     const int planes = in.nz > 1 ? 3 : 1;
     int ty = want_ty > 0 ? want_ty : 4;
     if (in.ny == 1)

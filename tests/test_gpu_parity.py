@@ -167,13 +167,13 @@ def test_every_pass_algorithm_gives_the_same_transform():
     try:
         for xq, eb in cases:
             r = oracle.qai(xq, eb)
-            for a1 in (0, 1, 2):
-                for a2 in (0, 1, 2, 3):
-                    qai.set_tuning(edt1_algo=[a1, a1], edt2_algo=[a2, a2])
-                    print(f"tuning edt1 {a1} edt2 {a2} shape {xq.shape}", flush=True)
-                    g = gpu_run(xq, eb)
-                    for k in KEYS:
-                        assert np.array_equal(g[k].astype(np.int64), r[k].astype(np.int64)), (k, a1, a2, xq.shape)
+            combos = [(a1, a2, 0) for a1 in (0, 1, 2) for a2 in (0, 1, 2, 3)] + [(1, 3, 4), (1, 3, 1)]
+            for a1, a2, rows in combos:
+                qai.set_tuning(edt1_algo=[a1, a1], edt2_algo=[a2, a2], seed_rows=rows)
+                print(f"tuning edt1 {a1} edt2 {a2} seed_rows {rows} shape {xq.shape}", flush=True)
+                g = gpu_run(xq, eb)
+                for k in KEYS:
+                    assert np.array_equal(g[k].astype(np.int64), r[k].astype(np.int64)), (k, a1, a2, rows, xq.shape)
     finally:
         qai.set_tuning(None)
     assert qai.get_tuning() == base
