@@ -686,6 +686,152 @@ __global__ __launch_bounds__(256) void k_env_window(EnvArgs a)
     }
 }
 
+// Streaming outward search for short owner distances (the first EDT, whose
+// sites are dense): one lane per column, 64 adjacent columns per wave, the
+// column read once in blocks of 8 rows into a per-wave ring of 32 rows in LDS.
+// A row is settled from the ring when its outward search (same order and tie
+// rule as k_env_window) ends within H rows; rows with no site within H rows
+// are settled after the sweep by the same search over the whole column, and a
+// column without any site stays at "no site".
+template <int AXIS, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_env_swin(EnvArgs a)
+{
+    constexpr int H = 8, RN = 32;
+    __shared__ uint32_t ring[WPB * RN * 64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint32_t* const rl = ring + wv * RN * 64 + lane;
+    const int n = (int)((AXIS == 1) ? a.ny : a.nz);
+    const int64_t stride = (AXIS == 1) ? a.nx : a.nx * a.ny;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    const uint64_t ngroups = (a.ntiles + WPB - 1) / WPB;
+
+    for (uint64_t t = blockIdx.x; t < ngroups; t += gridDim.x) {
+        const uint64_t tile = xcd_remap(t, ngroups) * WPB + wv;
+        if (tile >= a.ntiles)
+            continue;
+        const int64_t xb = (int64_t)(tile % (uint64_t)nxb), o = (int64_t)(tile / (uint64_t)nxb);
+        const int64_t x0 = xb * 64;
+        const bool valid = x0 + lane < a.nx;
+        const int64_t tb = ((AXIS == 1) ? o * a.nx * a.ny : o * a.nx) + x0;
+        const uint32_t* __restrict__ inb = a.win + tb;
+        uint32_t* const outb = a.w + tb;
+        const uint32_t us = (uint32_t)stride;
+        const uint32_t uc = valid ? (uint32_t)lane : 0u;
+        const int nb = (n + 7) >> 3;
+        int pf = 0x7fffffff, pl = -1; // first and last row left unresolved by the ring search
+        bool seen = false;            // any site in the column
+        uint32_t sm = 0u;             // bit (row & 31): that ring row holds a site
+
+        auto finalize = [&](int f) {
+            uint32_t best = rl[(f & (RN - 1)) * 64];
+            // no site within +-H rows: unresolved without searching
+            const bool near = (__builtin_rotateright32(sm, (uint32_t)(f - H) & 31u) & ((2u << (2 * H)) - 1u)) != 0u;
+            if ((best >> 2) != 0u && !near) {
+                pf = min(pf, f);
+                pl = f;
+            } else if ((best >> 2) != 0u) {
+                int d = 1;
+                for (; d <= H; ++d) {
+                    const uint32_t d2s = (uint32_t)d * (uint32_t)d << 2;
+                    if (d2s > (best | 3u))
+                        break;
+                    const int lo = f - d, hi = f + d;
+                    if (lo < 0 && hi >= n)
+                        break;
+                    if (lo >= 0) {
+                        const uint32_t cand = word_add(rl[(lo & (RN - 1)) * 64], d2s);
+                        if ((cand >> 2) <= (best >> 2))
+                            best = cand;
+                    }
+                    if (hi < n) {
+                        const uint32_t cand = word_add(rl[(hi & (RN - 1)) * 64], d2s);
+                        if ((cand >> 2) < (best >> 2))
+                            best = cand;
+                    }
+                }
+                if (d > H) {
+                    // unresolved inside the ring: settled after the sweep
+                    pf = min(pf, f);
+                    pl = f;
+                }
+            }
+            if (valid)
+                outb[(uint32_t)f * us + uc] = best;
+        };
+
+        uint32_t A[8], B[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            A[k] = inb[(uint32_t)min(k, n - 1) * us + uc];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            B[k] = inb[(uint32_t)min(8 + k, n - 1) * us + uc];
+        // block b: store rows 8b..8b+7 into the ring, prefetch block b+2, finalize block b-1
+        for (int b = 0; b < nb; b += 2) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                rl[(((b * 8) + k) & (RN - 1)) * 64] = A[k];
+                seen |= A[k] != QAI_WORD_INF;
+                sm = (A[k] != QAI_WORD_INF) ? (sm | (1u << (((b * 8) + k) & 31))) : (sm & ~(1u << (((b * 8) + k) & 31)));
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                A[k] = inb[(uint32_t)min((b + 2) * 8 + k, n - 1) * us + uc];
+            if (b >= 1)
+                for (int k = 0; k < 8; ++k)
+                    finalize((b - 1) * 8 + k);
+            if (b + 1 < nb) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    rl[(((b + 1) * 8 + k) & (RN - 1)) * 64] = B[k];
+                    seen |= B[k] != QAI_WORD_INF;
+                    sm = (B[k] != QAI_WORD_INF) ? (sm | (1u << (((b + 1) * 8 + k) & 31))) : (sm & ~(1u << (((b + 1) * 8 + k) & 31)));
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    B[k] = inb[(uint32_t)min((b + 3) * 8 + k, n - 1) * us + uc];
+                for (int k = 0; k < 8; ++k)
+                    finalize(b * 8 + k);
+            }
+        }
+        // the last block
+        for (int f = (nb - 1) * 8; f < n; ++f)
+            finalize(f);
+        // rows farther than H from every useful site: exact outward search over
+        // the whole column (a column without any site stays at "no site")
+        if (__ballot(seen && pl >= 0 && valid)) {
+            if (seen && pl >= 0 && valid) {
+                for (int f = pf; f <= pl; ++f) {
+                    uint32_t best = outb[(uint32_t)f * us + uc];
+                    if (best != QAI_WORD_INF && (best >> 2) < (uint32_t)((H + 1) * (H + 1)))
+                        continue;
+                    best = inb[(uint32_t)f * us + uc];
+                    for (int d = 1; d < n; ++d) {
+                        const uint32_t d2s = (uint32_t)d * (uint32_t)d << 2;
+                        if (d2s > (best | 3u))
+                            break;
+                        const int lo = f - d, hi = f + d;
+                        if (lo < 0 && hi >= n)
+                            break;
+                        if (lo >= 0) {
+                            const uint32_t cand = word_add(inb[(uint32_t)lo * us + uc], d2s);
+                            if ((cand >> 2) <= (best >> 2))
+                                best = cand;
+                        }
+                        if (hi < n) {
+                            const uint32_t cand = word_add(inb[(uint32_t)hi * us + uc], d2s);
+                            if ((cand >> 2) < (best >> 2))
+                                best = cand;
+                        }
+                    }
+                    outb[(uint32_t)f * us + uc] = best;
+                }
+            }
+        }
+    }
+}
+
 // RemoveEDT(g_u, g_v, g_w, u, v) with sites u < v < w (Section III-B): true
 // when v's cell between u and w is empty.  Products reach 2^44: int64.
 __device__ __forceinline__ bool remove_mid(uint32_t gu, uint32_t gv, uint32_t gw, int u, int v, int w)
@@ -1352,7 +1498,7 @@ void default_tuning(Tuning& t)
     for (int i = 0; i < 3; ++i) {
         t.env_tx_log2[i] = -1;
         t.env_algo[i] = 3;
-        t.edt1_algo[i] = 1;
+        t.edt1_algo[i] = 4;
         t.stream_cap[i] = 32;
         t.edt1_cap[i] = 16;
     }
@@ -1581,6 +1727,17 @@ static hipError_t launch_lane_t(EnvArgs a, int hb, bool small, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int AXIS>
+static hipError_t launch_swin_t(EnvArgs a, hipStream_t s)
+{
+    constexpr int WPB = 4;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    a.ntiles = (uint64_t)(nxb * (AXIS == 1 ? a.nz : a.ny));
+    const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
+    hipLaunchKernelGGL((k_env_swin<AXIS, WPB>), dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_t s)
 {
     const int64_t n = axis == 1 ? a.ny : a.nz;
@@ -1605,6 +1762,8 @@ hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_
     }
     if (t.env_algo[axis] == 2 && n <= 64 * 32)
         return launch_band2(axis, epi, a, t, s);
+    if (t.env_algo[axis] == 4 && !epi)
+        return axis == 1 ? launch_swin_t<1>(a, s) : launch_swin_t<2>(a, s);
     if (t.env_algo[axis] == 3 && !epi) {
         int hb;
         bool small;
