@@ -55,6 +55,10 @@ def main():
     ap.add_argument("--workload", default="grf512_k11/3_eb1e-3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-regime", action="store_true")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the 48-field uneven batch (graph launch vs per-field launches)")
+    ap.add_argument("--grad", action="store_true",
+                    help="also time forward + adjoint on the 256^3 field of the differentiable form")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -102,15 +106,20 @@ def main():
     copy_gbps = 10 * 8.0 * nvox / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
 
-    # timed region: K full post-passes, stage events on the launch stream
+    # timed region: K full post-passes, stage and step events on the launch stream
     qai.profile(True)
     qai.stage_times(reset=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    marks[0].record(stream)
+    for k in range(args.steps):
         qai.mitigate(field, eb, out=out, workspace=ws)
+        marks[k + 1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    step_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps))
+    trimmed = step_ms[1:-1] if len(step_ms) > 2 else step_ms
     stages = qai.stage_times(reset=True)
     qai.profile(False)
     ms_step = elapsed * 1e3 / args.steps
@@ -163,16 +172,86 @@ def main():
                      "frac_of_peak": round(total_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                      "frac_of_copy": round(total_alg / (ms_step * 1e-3) / 1e9 / copy_gbps, 4),
                      "copy_GBps": round(copy_gbps, 1), "stage_sum_ms": round(stage_sum_ms, 4),
-                     "stages_us": {k: round(v * 1e3, 1) for k, v in per_launch.items()}},
+                     "stages_us": {k: round(v * 1e3, 1) for k, v in per_launch.items()},
+                     "step_ms_median": round(float(np.median(step_ms)), 4),
+                     "step_ms_trimmed_mean": round(float(np.mean(trimmed)), 4)},
     }
 
     if not args.no_regime:
         res["regime"] = regime_stats(qai, field, x32, eb, dev)
 
+    if args.grad:
+        res["differentiable"] = bench_grad(qai, synth, dev, args.steps, args.warmup)
+    if args.batched:
+        del field, out, ws
+        torch.cuda.empty_cache()
+        res["batched"] = bench_batched(qai, synth, dev, max(3, args.steps // 4))
+
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(xq, eb)
 
     print(json.dumps(res), flush=True)
+
+
+def _time(fn, reps, stream):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bench_grad(qai, synth, dev, steps, warmup):
+    """Forward (workspace kept) + adjoint on the 256^3 differentiable-form field."""
+    import torch
+    name = "grf256_k3_eb5e-3"
+    x32, xq, q, eb = synth.make_workload(name)
+    n = int(np.prod(xq.shape))
+    t = torch.from_numpy(xq).to(dev)
+    out = torch.empty_like(t)
+    ws = qai.new_workspace(t.shape, dev)
+    g = torch.randn_like(t)
+    s = torch.cuda.current_stream()
+    for _ in range(warmup):
+        qai.mitigate(t, eb, out=out, workspace=ws)
+        qai.backward(g, ws, t.shape, eb)
+    fwd = _time(lambda: qai.mitigate(t, eb, out=out, workspace=ws), steps, s)
+    bwd = _time(lambda: qai.backward(g, ws, t.shape, eb), steps, s)
+    log(f"differentiable {name}: forward {fwd:.3f} ms, adjoint {bwd:.3f} ms")
+    return {"workload": name, "voxels": n, "forward_ms": round(fwd, 4), "adjoint_ms": round(bwd, 4),
+            "adjoint_GBps_alg": round(12.0 * n / (bwd * 1e-3) / 1e9, 1)}
+
+
+def bench_batched(qai, synth, dev, reps):
+    """The 48-field uneven batch: one graph launch vs the same kernels launched
+    field by field (autotuned per shape)."""
+    import torch
+    t0 = time.time()
+    fields, ebs = [], []
+    for spec in synth.batch_specs():
+        x32, xq, q, eb = synth.make_batch_field(spec)
+        fields.append(torch.from_numpy(xq).to(dev))
+        ebs.append(eb)
+    nvox = sum(int(f.numel()) for f in fields)
+    log(f"batch of {len(fields)} fields, {nvox} voxels, generated in {time.time() - t0:.1f}s")
+    plan = qai.BatchPlan(fields, ebs, autotune=True)
+    s = torch.cuda.current_stream()
+    plan.launch()
+    plan.launch_per_field()
+    graph_ms = _time(plan.launch, reps, s)
+    per_ms = _time(plan.launch_per_field, reps, s)
+    tunes = {}
+    for i, f in enumerate(fields):
+        tunes.setdefault("x".join(map(str, f.shape)), plan.tuning(i))
+    plan.close()
+    log(f"batched: graph {graph_ms:.2f} ms, per-field launches {per_ms:.2f} ms")
+    return {"fields": len(fields), "voxels": nvox, "graph_ms": round(graph_ms, 3), "per_field_ms": round(per_ms, 3),
+            "value": round(4.0 * nvox / (graph_ms * 1e-3) / 1e9, 2), "unit": "GB/s",
+            "per_field_GBps": round(4.0 * nvox / (per_ms * 1e-3) / 1e9, 2), "tuning": tunes}
 
 
 def kernel_rev():

@@ -129,27 +129,47 @@ const char* qai_last_error(void);
 
 /* ------------------------------------------------------------------ batch
  * Batched form (project addition, not in the paper): many fields of uneven
- * shapes in one persistent kernel, captured once in a hipGraph and replayed.
- * Each field's result is bit-identical to qai_mitigate_ex on it alone. */
+ * shapes processed by one hipGraph launch.  Each field runs the plain
+ * pipeline on its own slice of the workspace; fields are dealt, largest
+ * first, to up to four independent branches of the graph, so kernels of
+ * different fields overlap.  Each field's result is bit-identical to
+ * qai_mitigate_ex on it alone. */
 typedef struct qai_batch_plan qai_batch_plan;
 
-/* Bytes of device workspace a batch of n fields needs. */
+/* Plan flag: before capturing, time a small set of launch settings (pass
+ * algorithms, seed variant and z-march) on the first field of each distinct
+ * shape and use the fastest for every field of that shape. */
+#define QAI_BATCH_AUTOTUNE 0x1u
+
+/* Bytes of device workspace a batch of n fields needs: the sum over fields
+ * of qai_workspace_bytes, each rounded up to 256.  0 for invalid input. */
 size_t qai_batch_workspace_bytes(int n, const int64_t (*dims)[3]);
 
-/* Build a plan: validates every field, uploads a descriptor table into ws,
- * and captures the persistent launch into a graph on stream.  fields/outs
- * are arrays of n device pointers, dims n host triples, ebs n host floats.
- * The plan keeps the raw pointers until qai_batch_plan_destroy. */
+/* Build a plan and capture it into a graph.
+ *   fields, outs  arrays of n device FP32 pointers (an output may not overlap
+ *                 its input)
+ *   dims, ebs     n host triples {nz, ny, nx} and n host error bounds
+ *   params        shared step-E parameters (NULL = defaults)
+ *   flags         0 or QAI_BATCH_AUTOTUNE (autotuning runs the pipeline on
+ *                 the first field of each shape, writing its output)
+ *   ws, ws_bytes  device workspace of qai_batch_workspace_bytes, 256-aligned
+ *   stream        stream for the autotuning runs; synchronised before capture
+ * The plan keeps the raw pointers until qai_batch_plan_destroy; the settings
+ * are fixed at creation (qai_tuning_set afterwards does not change them). */
 int qai_batch_plan_create(int n, const float* const* fields, const int64_t (*dims)[3], const float* ebs,
-                          float* const* outs, const qai_params* params, void* ws, size_t ws_bytes,
+                          float* const* outs, const qai_params* params, uint32_t flags, void* ws, size_t ws_bytes,
                           void* stream, qai_batch_plan** plan);
 
 /* Replay the captured graph on stream (hipGraphLaunch). */
 int qai_batch_plan_launch(qai_batch_plan* plan, void* stream);
 
-/* Run the same batch without the graph, as one launch per stage per field
- * (the reference point the persistent form is compared with). */
+/* Run the same batch without the graph, one launch per stage per field, in
+ * field order on stream (the reference point the graph is compared with). */
 int qai_batch_plan_launch_per_field(qai_batch_plan* plan, void* stream);
+
+/* The launch setting the plan uses for field (after autotuning). */
+typedef struct qai_tuning qai_tuning;
+int qai_batch_plan_tuning(const qai_batch_plan* plan, int field, qai_tuning* t);
 
 void qai_batch_plan_destroy(qai_batch_plan* plan);
 
@@ -157,7 +177,7 @@ void qai_batch_plan_destroy(qai_batch_plan* plan);
  * Launch geometry and per-pass algorithm choice (process-wide; the batched
  * plan captures the setting current at its creation).  Results do not depend
  * on it: every choice computes the same exact transforms. */
-typedef struct {
+typedef struct qai_tuning {
     int32_t edt1_algo[2];  /* y and z passes of the first EDT: 0 streaming envelope, 1 windowed
                               search over LDS tiles, 2 banded envelope over LDS tiles,
                               4 streaming outward search (short distances; the default) */

@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import QAIError, QAI_STATUS_QRANGE  # noqa: F401
 
 __all__ = ["mitigate", "workspace_bytes", "device_status", "backward", "QAIFunction", "fit_params",
-           "copy_probe", "profile", "stage_times", "QAIError", "lib"]
+           "BatchPlan", "mitigate_batched", "copy_probe", "profile", "stage_times", "QAIError", "lib"]
 
 
 def lib():
@@ -166,6 +166,78 @@ def fit_params(x_dec, x_orig, eb, steps=50, eta0=0.9, power0=1.0, lr=0.05, fit_p
             pw.clamp_(min=0.05)
         hist.append(float(loss.detach()))
     return float(eta.detach()), float(pw.detach()), hist
+
+
+class BatchPlan:
+    """Batched form: many float32 CUDA fields of uneven shapes run by one
+    hipGraph launch (``qai_batch_plan_*``).  ``outs`` and the workspace are
+    allocated here unless given; the plan keeps references to every tensor it
+    uses.  ``autotune=True`` times a few launch settings on the first field of
+    each distinct shape before capture (results are unchanged by it)."""
+
+    def __init__(self, fields, ebs, outs=None, eta=0.9, power=1.0, autotune=True, workspace=None, stream=None):
+        L = lib()
+        if len(fields) != len(ebs) or not fields:
+            raise ValueError("one error bound per field, at least one field")
+        self.fields = list(fields)
+        for f in self.fields:
+            _check_field(f)
+        self.outs = list(outs) if outs is not None else [torch.empty_like(f) for f in self.fields]
+        n = len(self.fields)
+        dims = (_lib.Dims * n)(*[_lib.dims3(f.shape) for f in self.fields])
+        need = int(L.qai_batch_workspace_bytes(n, dims))
+        if need == 0:
+            raise QAIError(-2, "invalid field shapes")
+        dev = self.fields[0].device
+        self.workspace = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8, device=dev)
+        fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in self.fields])
+        op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in self.outs])
+        eb = (ctypes.c_float * n)(*[float(e) for e in ebs])
+        prm = _lib.Params(float(eta), float(power), 0)
+        h = ctypes.c_void_p()
+        _lib.check(L.qai_batch_plan_create(n, fp, dims, eb, op, ctypes.byref(prm),
+                                           _lib.QAI_BATCH_AUTOTUNE if autotune else 0,
+                                           ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                           _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.n = n
+
+    def launch(self, stream=None):
+        """Replay the graph: every output is (re)written."""
+        _lib.check(lib().qai_batch_plan_launch(self._h, _stream_ptr(stream)))
+        return self.outs
+
+    def launch_per_field(self, stream=None):
+        """The same batch as separate launches, field after field."""
+        _lib.check(lib().qai_batch_plan_launch_per_field(self._h, _stream_ptr(stream)))
+        return self.outs
+
+    def tuning(self, i):
+        t = _lib.Tuning()
+        _lib.check(lib().qai_batch_plan_tuning(self._h, int(i), ctypes.byref(t)))
+        return {k: (list(getattr(t, k)) if hasattr(getattr(t, k), "__len__") else int(getattr(t, k)))
+                for k in TUNING_FIELDS}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().qai_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mitigate_batched(fields, ebs, eta=0.9, power=1.0, autotune=False, stream=None):
+    """Run the post-pass on a list of fields with one graph launch; returns
+    the list of outputs."""
+    plan = BatchPlan(fields, ebs, eta=eta, power=power, autotune=autotune, stream=stream)
+    outs = plan.launch(stream)
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    plan.close()
+    return outs
 
 
 def copy_probe(src, dst, stream=None):

@@ -15,6 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libqai.so")
 
 QAI_OK = 0
+QAI_BATCH_AUTOTUNE = 0x1
 ERRORS = {-1: "QAI_EINVAL", -2: "QAI_EDIMS", -3: "QAI_ENOWS", -4: "QAI_EHIP", -5: "QAI_ENODEV",
           -6: "QAI_ESTATE"}
 QAI_STATUS_QRANGE = 0x1
@@ -45,7 +46,7 @@ Dims = ctypes.c_int64 * 3
 
 EXPORTS = ["qai_mitigate", "qai_workspace_bytes", "qai_mitigate_ex", "qai_backward", "qai_device_status",
            "qai_last_error", "qai_batch_workspace_bytes", "qai_batch_plan_create", "qai_batch_plan_launch",
-           "qai_batch_plan_launch_per_field", "qai_batch_plan_destroy", "qai_copy_probe",
+           "qai_batch_plan_launch_per_field", "qai_batch_plan_tuning", "qai_batch_plan_destroy", "qai_copy_probe",
            "qai_profile_enable", "qai_stage_times", "qai_tuning_get", "qai_tuning_set"]
 
 _lib = None
@@ -72,8 +73,9 @@ def load(path=LIB_PATH):
     lib.qai_batch_workspace_bytes.argtypes = [I, ctypes.POINTER(Dims)]
     lib.qai_batch_workspace_bytes.restype = SZ
     lib.qai_batch_plan_create.argtypes = [I, ctypes.POINTER(P), ctypes.POINTER(Dims), ctypes.POINTER(F),
-                                          ctypes.POINTER(P), ctypes.POINTER(Params), P, SZ, P,
+                                          ctypes.POINTER(P), ctypes.POINTER(Params), ctypes.c_uint32, P, SZ, P,
                                           ctypes.POINTER(P)]
+    lib.qai_batch_plan_tuning.argtypes = [P, I, ctypes.POINTER(Tuning)]
     lib.qai_batch_plan_launch.argtypes = [P, P]
     lib.qai_batch_plan_launch_per_field.argtypes = [P, P]
     lib.qai_batch_plan_destroy.argtypes = [P]

@@ -14,7 +14,8 @@
 #include "qai_device.h"
 #include "qai_kernels.h"
 
-namespace {
+namespace qai {
+namespace api {
 
 thread_local std::string g_err;
 
@@ -33,8 +34,6 @@ int fail_hip(hipError_t e, const char* what)
 {
     return fail(QAI_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
-
-constexpr size_t kHeader = 64 * 1024;
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -74,6 +73,13 @@ int check_params(const qai_params* p, qai_params* out)
     return QAI_OK;
 }
 
+} // namespace api
+} // namespace qai
+
+using namespace qai::api;
+
+namespace {
+
 // ---- stage timing
 struct StageRec {
     const char* name;
@@ -94,6 +100,7 @@ qai::Tuning current_tuning()
     return g_tune;
 }
 bool g_prof_on = false;
+thread_local int g_prof_suppress = 0; // stage timing paused (graph capture)
 std::vector<StageRec> g_pending;
 std::vector<std::pair<const char*, double>> g_acc;
 thread_local hipEvent_t g_cur_a = nullptr;
@@ -105,7 +112,7 @@ namespace qai {
 
 void prof_begin(const char* name, hipStream_t s)
 {
-    if (!g_prof_on)
+    if (!g_prof_on || g_prof_suppress)
         return;
     hipEvent_t a;
     if (hipEventCreate(&a) != hipSuccess)
@@ -117,7 +124,7 @@ void prof_begin(const char* name, hipStream_t s)
 
 void prof_end(hipStream_t s)
 {
-    if (!g_prof_on || !g_cur_a)
+    if (!g_prof_on || g_prof_suppress || !g_cur_a)
         return;
     hipEvent_t b;
     if (hipEventCreate(&b) != hipSuccess)
@@ -127,6 +134,43 @@ void prof_end(hipStream_t s)
     g_pending.push_back({g_cur_name, g_cur_a, b});
     g_cur_a = nullptr;
 }
+
+namespace api {
+
+Tuning tuning_now() { return current_tuning(); }
+
+void prof_suppress(bool on) { g_prof_suppress += on ? 1 : -1; }
+
+uint32_t* word_buffer(void* ws, int64_t n, int k)
+{
+    return (uint32_t*)((unsigned char*)ws + kHeaderBytes + (size_t)k * align256((size_t)n * 4));
+}
+
+void ws_buffers(void* ws, int64_t n, Plan1& p)
+{
+    p.status = (uint32_t*)ws;
+    p.bufA = word_buffer(ws, n, 0);
+    p.bufB = word_buffer(ws, n, 1);
+    p.bufC = word_buffer(ws, n, 2);
+}
+
+int tuning_to_abi(const Tuning& t, qai_tuning* out)
+{
+    out->edt1_algo[0] = t.edt1_algo[1];
+    out->edt1_algo[1] = t.edt1_algo[2];
+    out->edt2_algo[0] = t.env_algo[1];
+    out->edt2_algo[1] = t.env_algo[2];
+    out->edt1_ring = t.edt1_cap[1];
+    out->edt2_ring = t.stream_cap[1];
+    out->tile_log2[0] = t.env_tx_log2[1];
+    out->tile_log2[1] = t.env_tx_log2[2];
+    out->seed_rows = t.seed_ty;
+    out->seed_planes = t.seed_tz;
+    out->window_threads = t.env_threads;
+    return QAI_OK;
+}
+
+} // namespace api
 
 hipError_t launch_backward(const float* g, const uint32_t* w1, const uint32_t* w2, int64_t n, float eb, float eta,
                            float power, double* partial, float* out, hipStream_t s);
@@ -138,10 +182,6 @@ namespace {
 
 constexpr size_t kPartialOffset = 256; // FP64 partial sums of the adjoint reduction
 
-uint32_t* word_buffer(void* ws, int64_t n, int k)
-{
-    return (uint32_t*)((unsigned char*)ws + kHeader + (size_t)k * align256((size_t)n * 4));
-}
 
 int plain_checked(const float* field, const int64_t dims[3], float eb, const qai_params* params, void* ws,
                   size_t ws_bytes, float* out, const qai_taps* taps, void* stream)
@@ -179,10 +219,7 @@ int plain_checked(const float* field, const int64_t dims[3], float eb, const qai
     pl.eb = eb;
     pl.eta = p.eta;
     pl.power = p.power;
-    pl.status = (uint32_t*)ws;
-    pl.bufA = word_buffer(ws, n, 0);
-    pl.bufB = word_buffer(ws, n, 1);
-    pl.bufC = word_buffer(ws, n, 2);
+    ws_buffers(ws, n, pl);
     if (taps)
         pl.taps = *taps;
     const qai::Tuning t = current_tuning();
@@ -218,7 +255,7 @@ size_t qai_workspace_bytes(const int64_t dims[3])
         if (dims[a] < 1 || dims[a] > QAI_MAX_EXTENT)
             return 0;
     n = dims[0] * dims[1] * dims[2];
-    return kHeader + 3 * align256((size_t)n * 4);
+    return kHeaderBytes + 3 * align256((size_t)n * 4);
 }
 
 int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const qai_params* params, void* ws,
@@ -325,19 +362,7 @@ int qai_tuning_get(qai_tuning* out)
     g_err.clear();
     if (!out)
         return fail(QAI_EINVAL, "tuning pointer is NULL");
-    const qai::Tuning t = current_tuning();
-    out->edt1_algo[0] = t.edt1_algo[1];
-    out->edt1_algo[1] = t.edt1_algo[2];
-    out->edt2_algo[0] = t.env_algo[1];
-    out->edt2_algo[1] = t.env_algo[2];
-    out->edt1_ring = t.edt1_cap[1];
-    out->edt2_ring = t.stream_cap[1];
-    out->tile_log2[0] = t.env_tx_log2[1];
-    out->tile_log2[1] = t.env_tx_log2[2];
-    out->seed_rows = t.seed_ty;
-    out->seed_planes = t.seed_tz;
-    out->window_threads = t.env_threads;
-    return QAI_OK;
+    return tuning_to_abi(current_tuning(), out);
 }
 
 int qai_tuning_set(const qai_tuning* in)

@@ -100,4 +100,20 @@ hipError_t run_plain(Plan1& p, const Tuning& t, hipStream_t s);
 void prof_begin(const char* name, hipStream_t s);
 void prof_end(hipStream_t s);
 
+// Host-side helpers of the C ABI shared by the plain and batched entry points.
+namespace api {
+constexpr size_t kHeaderBytes = 64 * 1024; // status word at 0, adjoint partial sums at 256
+int fail(int code, const char* fmt, ...);
+int fail_hip(hipError_t e, const char* what);
+size_t align256(size_t v);
+int check_dims(const int64_t dims[3], int64_t* n);
+int check_eb(float eb);
+int check_params(const qai_params* p, qai_params* out);
+Tuning tuning_now();
+void prof_suppress(bool on);               // pause stage timing on this thread (nests)
+uint32_t* word_buffer(void* ws, int64_t n, int k);
+void ws_buffers(void* ws, int64_t n, Plan1& p); // status word and the three word buffers
+int tuning_to_abi(const Tuning& t, qai_tuning* out);
+} // namespace api
+
 } // namespace qai

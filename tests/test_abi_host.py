@@ -85,3 +85,31 @@ def test_no_device_is_reported_without_a_launch(lib):
         pass
     assert call_ex(lib) == -5
     assert "GPU" in lib.qai_last_error().decode()
+
+
+def test_batch_workspace_and_argument_errors(lib):
+    dims = (_lib.Dims * 3)(_lib.Dims(4, 5, 6), _lib.Dims(1, 1, 1000), _lib.Dims(2, 300, 7))
+    want = sum(((lib.qai_workspace_bytes(dims[i]) + 255) // 256) * 256 for i in range(3))
+    assert lib.qai_batch_workspace_bytes(3, dims) == want
+    assert lib.qai_batch_workspace_bytes(0, dims) == 0
+    bad = (_lib.Dims * 1)(_lib.Dims(4, 0, 6))
+    assert lib.qai_batch_workspace_bytes(1, bad) == 0
+    P = ctypes.c_void_p
+    fp = (P * 1)(0x1000)
+    op = (P * 1)(0x100000)
+    eb = (ctypes.c_float * 1)(0.5)
+    d1 = (_lib.Dims * 1)(_lib.Dims(4, 5, 6))
+    h = ctypes.c_void_p()
+    big = 1 << 30
+    assert lib.qai_batch_plan_create(0, fp, d1, eb, op, None, 0, FAKE, big, None, ctypes.byref(h)) == -1
+    assert lib.qai_batch_plan_create(1, fp, d1, eb, op, None, 2, FAKE, big, None, ctypes.byref(h)) == -1
+    assert lib.qai_batch_plan_create(1, fp, bad, eb, op, None, 0, FAKE, big, None, ctypes.byref(h)) == -2
+    ebz = (ctypes.c_float * 1)(0.0)
+    assert lib.qai_batch_plan_create(1, fp, d1, ebz, op, None, 0, FAKE, big, None, ctypes.byref(h)) == -1
+    same = (P * 1)(0x1000)
+    assert lib.qai_batch_plan_create(1, fp, d1, eb, same, None, 0, FAKE, big, None, ctypes.byref(h)) == -1
+    assert lib.qai_batch_plan_create(1, fp, d1, eb, op, None, 0, None, big, None, ctypes.byref(h)) == -3
+    assert lib.qai_batch_plan_create(1, fp, d1, eb, op, None, 0, FAKE, 10, None, ctypes.byref(h)) == -3
+    assert h.value is None
+    assert lib.qai_batch_plan_launch(None, None) == -6
+    assert lib.qai_batch_plan_tuning(None, 0, None) == -1

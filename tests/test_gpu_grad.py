@@ -1,0 +1,141 @@
+"""Differentiable form (project addition): the adjoint of step E on the GPU
+against an FP64 CPU autograd reference, against central finite differences of
+the GPU forward, and the per-field fit against the closed-form optimum of eta.
+
+The reference takes the exact distance transforms and signs from the CPU oracle
+and writes step E (Section V) out in float64 torch, so autograd differentiates
+w = k1^-p / (k1^-p + k2^-p) with the pinned cases held constant."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_20097_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def reference_out(xq, eb, r, eta, power):
+    """Step E in float64 torch from the oracle's transforms; eta and power are
+    0-dim float64 tensors (possibly requiring grad)."""
+    d1 = torch.from_numpy(r["d1sq"].astype(np.float64))
+    d2 = torch.from_numpy(r["d2sq"].astype(np.float64))
+    s = torch.from_numpy(r["s"].astype(np.float64))
+    x = torch.from_numpy(xq.astype(np.float64))
+    on_b1 = d1 == 0
+    on_b2 = d2 == 0
+    no_b2 = d2 < 0
+    no_b1 = d1 < 0
+    general = ~(on_b1 | on_b2 | no_b2 | no_b1)
+    k1 = torch.sqrt(torch.where(general, d1, torch.ones_like(d1)))
+    k2 = torch.sqrt(torch.where(general, d2, torch.ones_like(d2)))
+    wg = 1.0 / (1.0 + (k1 / k2) ** power)
+    w = torch.where(on_b1 | (no_b2 & ~on_b2), torch.ones_like(d1), torch.zeros_like(d1))
+    w = torch.where(general, wg, w)
+    return x + w * s * eta * float(eb)
+
+
+def field(shape=(24, 40, 56), rel=2e-2, seed=11):
+    x32, xq, q, eb = synth.quantize(synth.grf(shape, 3.0, seed), rel)
+    return x32, xq, eb
+
+
+def gpu_backward(xq, eb, g, eta, power):
+    import paper_2602_20097_amd as qai
+    t = torch.from_numpy(xq).cuda()
+    ws = qai.new_workspace(t.shape)
+    out = qai.mitigate(t, eb, eta, power, workspace=ws)
+    grad = qai.backward(torch.from_numpy(g).cuda(), ws, t.shape, eb, eta, power)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), grad.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("eta,power", [(0.9, 1.0), (0.6, 2.0), (1.1, 0.5)])
+def test_adjoint_matches_fp64_autograd(eta, power):
+    x32, xq, eb = field()
+    r = oracle.qai(xq, eb, eta, power)
+    g = np.random.default_rng(7).standard_normal(xq.shape).astype(np.float32)
+    e = torch.tensor(float(np.float32(eta)), dtype=torch.float64, requires_grad=True)
+    p = torch.tensor(float(np.float32(power)), dtype=torch.float64, requires_grad=True)
+    out_ref = reference_out(xq, eb, r, e, p)
+    # the reference forward is the oracle's step E
+    np.testing.assert_allclose(out_ref.detach().numpy(), r["out"], rtol=0, atol=1e-12)
+    loss = (torch.from_numpy(g.astype(np.float64)) * out_ref).sum()
+    loss.backward()
+    _, grad = gpu_backward(xq, eb, g, eta, power)
+    # each term carries the FP32 error of w (a few ulp): allow 1e-5 of the sum of |terms|
+    w = r["w"]
+    gen = (r["d1sq"] > 0) & (r["d2sq"] > 0)
+    lr = np.zeros_like(w)
+    lr[gen] = 0.5 * (np.log(r["d1sq"][gen].astype(np.float64)) - np.log(r["d2sq"][gen].astype(np.float64)))
+    gs = g.astype(np.float64) * r["s"]
+    scale_e = float(np.abs(gs * w * eb).sum())
+    scale_p = float(np.abs(gs * float(np.float32(eta)) * eb * w * (1 - w) * lr).sum())
+    print(f"d/deta gpu {grad[0]:.9g} ref {e.grad.item():.9g}; d/dp gpu {grad[1]:.9g} ref {p.grad.item():.9g}")
+    assert abs(grad[0] - e.grad.item()) <= 1e-5 * scale_e + 1e-12
+    assert abs(grad[1] - p.grad.item()) <= 1e-5 * scale_p + 1e-12
+
+
+def test_adjoint_matches_finite_differences_of_the_gpu_forward():
+    import paper_2602_20097_amd as qai
+    x32, xq, eb = field(shape=(32, 48, 64), seed=12)
+    g32 = np.random.default_rng(8).standard_normal(xq.shape).astype(np.float32)
+    g = g32.astype(np.float64)
+    t = torch.from_numpy(xq).cuda()
+
+    def loss(eta, power):
+        out = qai.mitigate(t, eb, eta, power).cpu().numpy().astype(np.float64)
+        return float((g * (out - xq.astype(np.float64))).sum())
+
+    _, grad = gpu_backward(xq, eb, g32, 0.9, 1.0)
+    h = 0.05
+    fd_eta = (loss(0.9 + h, 1.0) - loss(0.9 - h, 1.0)) / (2 * h)
+    fd_pow = (loss(0.9, 1.0 + h) - loss(0.9, 1.0 - h)) / (2 * h)
+    assert fd_eta == pytest.approx(grad[0], rel=2e-3)
+    assert fd_pow == pytest.approx(grad[1], rel=2e-2)
+
+
+def test_gradient_to_the_decompressed_values_is_the_identity():
+    import paper_2602_20097_amd as qai
+    x32, xq, eb = field(shape=(8, 20, 30), seed=13)
+    x = torch.from_numpy(xq).cuda().requires_grad_(True)
+    eta = torch.tensor(0.9, device="cuda", requires_grad=True)
+    pw = torch.tensor(1.0, device="cuda", requires_grad=True)
+    y = qai.QAIFunction.apply(x, eta, pw, eb)
+    g = torch.randn_like(y)
+    (y * g).sum().backward()
+    assert torch.equal(x.grad, g)
+    ref = qai.backward(g.contiguous(), _ws_of(qai, xq, eb), xq.shape, eb)
+    torch.cuda.synchronize()
+    assert float(eta.grad) == pytest.approx(float(ref[0]), rel=1e-6)
+    assert float(pw.grad) == pytest.approx(float(ref[1]), rel=1e-6)
+
+
+def _ws_of(qai, xq, eb):
+    t = torch.from_numpy(xq).cuda()
+    ws = qai.new_workspace(t.shape)
+    qai.mitigate(t, eb, workspace=ws)
+    return ws
+
+
+def test_fit_reaches_the_closed_form_eta_on_the_256_cube():
+    """With p fixed, out is affine in eta, so the MSE optimum is
+    eta* = sum(a (x - x')) / sum(a^2) with a = w S eb; a 50-step fit lands on it."""
+    import paper_2602_20097_amd as qai
+    x32, xq, q, eb = synth.make_workload("grf256_k3_eb5e-3")
+    t = torch.from_numpy(xq).cuda()
+    xo = torch.from_numpy(x32).cuda()
+    _, taps = qai.mitigate(t, eb, taps=True)
+    a = taps["w"].double() * taps["s"].double() * float(eb)
+    eta_star = float((a * (xo.double() - t.double())).sum() / (a * a).sum())
+    mse = lambda e: float(((t.double() + e * a - xo.double()) ** 2).mean())  # noqa: E731
+    eta_fit, p_fit, hist = qai.fit_params(t, xo, eb, steps=50, fit_power=False, lr=0.05)
+    print(f"eta* = {eta_star:.5f}, fitted {eta_fit:.5f}, mse {hist[0]:.4e} -> {hist[-1]:.4e}", flush=True)
+    assert p_fit == 1.0
+    assert abs(eta_fit - eta_star) <= 0.05 * max(1.0, abs(eta_star))
+    assert hist[-1] <= hist[0]
+    assert mse(eta_fit) <= mse(eta_star) * (1 + 5e-3)
+    # fitting the power as well never ends above the eta-only optimum by more than noise
+    eta2, p2, hist2 = qai.fit_params(t, xo, eb, steps=50, fit_power=True, lr=0.05)
+    assert hist2[-1] <= hist2[0]
+    assert hist2[-1] <= mse(eta_star) * (1 + 5e-2)
