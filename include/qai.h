@@ -180,10 +180,13 @@ void qai_batch_plan_destroy(qai_batch_plan* plan);
 typedef struct qai_tuning {
     int32_t edt1_algo[2];  /* y and z passes of the first EDT: 0 streaming envelope, 1 windowed
                               search over LDS tiles, 2 banded envelope over LDS tiles,
-                              4 streaming outward search (short distances; the default) */
+                              4 streaming outward search (short distances); -1 (the default)
+                              picks per pass: 1 when the pass has fewer than 1024 tiles of
+                              64 columns, else 4 */
     int32_t edt2_algo[2];  /* the same for the second EDT, plus 3: per-lane online envelope
                               (payload-free words; falls back to 0 where its packed ring
-                              entries would not fit 32 bits; the default) */
+                              entries would not fit 32 bits); -1 (the default) picks 1 below
+                              1024 tiles, else 3 */
     int32_t edt1_ring;     /* live-window ring entries of the streaming envelope: 16, 32 or 64 */
     int32_t edt2_ring;
     int32_t tile_log2[2];  /* log2 of x-columns per tile of the tiled variants, y and z (-1: auto) */

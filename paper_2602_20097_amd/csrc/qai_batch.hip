@@ -63,7 +63,7 @@ void release(qai_batch_plan* p)
 std::vector<qai::Tuning> candidates(const qai::Tuning& base, int64_t nx)
 {
     std::vector<qai::Tuning> out;
-    const int e1s[2] = {4, 1}, e2s[2] = {3, 0};
+    const int e1s[3] = {-1, 4, 1}, e2s[3] = {-1, 3, 1};
     const int seeds[3][2] = {{0, 16}, {0, 32}, {4, 16}};
     for (int a : e1s)
         for (int b : e2s)

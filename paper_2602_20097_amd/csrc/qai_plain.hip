@@ -1497,8 +1497,8 @@ void default_tuning(Tuning& t)
 {
     for (int i = 0; i < 3; ++i) {
         t.env_tx_log2[i] = -1;
-        t.env_algo[i] = 3;
-        t.edt1_algo[i] = 4;
+        t.env_algo[i] = -1; // chosen per pass from its parallelism (see resolve_algo)
+        t.edt1_algo[i] = -1;
         t.stream_cap[i] = 32;
         t.edt1_cap[i] = 16;
     }
@@ -1822,8 +1822,27 @@ void final_buffers(int64_t nz, int64_t ny, int64_t nx, int& w1, int& w2)
             return e_;                  \
     } while (0)
 
-hipError_t run_plain(Plan1& p, const Tuning& t, hipStream_t s)
+// Automatic pass algorithm: the streaming kernels give one wavefront to 64
+// columns and walk the whole column, so they need many column tiles to fill
+// the GPU; a pass with fewer tiles than SIMDs (e.g. the y pass of a 2-D field)
+// takes the windowed search, which is parallel over every voxel.
+static int resolve_algo(int want, bool first_edt, int axis, int64_t nz, int64_t ny, int64_t nx)
 {
+    if (want >= 0)
+        return want;
+    const int64_t tiles = ((nx + 63) / 64) * (axis == 1 ? nz : ny);
+    if (tiles < 1024)
+        return 1;
+    return first_edt ? 4 : 3;
+}
+
+hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
+{
+    Tuning t = t_in;
+    for (int a = 1; a <= 2; ++a) {
+        t.edt1_algo[a] = resolve_algo(t_in.edt1_algo[a], true, a, p.nz, p.ny, p.nx);
+        t.env_algo[a] = resolve_algo(t_in.env_algo[a], false, a, p.nz, p.ny, p.nx);
+    }
     uint32_t* buf[3] = {p.bufA, p.bufB, p.bufC};
     prof_begin("clear", s);
     QAI_TRY(launch_clear(p.status, 1, s));
