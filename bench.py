@@ -39,6 +39,7 @@ STAGE_BYTES = {
     "edt2_y": 8,
     "edt2_z": 8,
     "interp": 16,         # read second-EDT words, first-EDT words, x'; write out
+    "edt2_z_interp": 16,  # fused last pass: read y-pass words, first-EDT words, x'; write out
     "clear": 0,
 }
 

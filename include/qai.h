@@ -91,9 +91,11 @@ typedef struct {
  * that must not allocate use qai_mitigate_ex. */
 int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out, void* stream);
 
-/* Bytes of device workspace qai_mitigate_ex needs for dims: three 32-bit
- * words per voxel (the packed distance words of the passes, ping-ponged) plus
- * a 64 KiB header (status word, reduction partials).  0 for invalid dims. */
+/* Bytes of device workspace qai_mitigate_ex needs for dims: a 64 KiB header
+ * (status word, reduction partials), three 32-bit words per voxel (the packed
+ * distance words of the passes, ping-ponged) and one bit per voxel (16-bit
+ * words per 16 z-rows of each column, used by the fused final pass), each part
+ * rounded up to 256 bytes.  0 for invalid dims. */
 size_t qai_workspace_bytes(const int64_t dims[3]);
 
 /* qai_mitigate_ex -- as qai_mitigate with explicit parameters (NULL = the

@@ -45,6 +45,7 @@ struct EnvArgs {
     float eta_eb, power;
     int32_t* td2;
     float* tw;
+    uint16_t* need;       // fused final pass: per column, one bit per row of "step E needs d2 here"
 };
 
 struct InterpArgs {
@@ -90,6 +91,7 @@ struct Plan1 {
     uint32_t* bufB;
     uint32_t* bufC;
     uint32_t* status;
+    uint16_t* need;       // scratch bitmap of the fused final pass (N/16 words)
     qai_taps taps;
     const uint32_t* w1_final;
     const uint32_t* w2_final;

@@ -1477,6 +1477,271 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane(EnvArgs a, int hb)
     }
 }
 
+// The second EDT's last pass (z) fused with step E.  The weight needs the
+// distance to B2 only where S != 0 off B1 ("needed" voxels); everywhere else
+// out = x' (S = 0) or x' + S eta eb (on B1, w = 1).  So every row's output is
+// written as the sweep reads it (needed rows provisionally with x'), and the
+// online envelope of k_env_lane emits only needed rows: the lane keeps its
+// oldest pending needed row e (with its x' and first-EDT word), and when e is
+// final it writes out[e] and the distance word of e (which the adjoint reads),
+// then moves e to the next needed row it has read.  Needed rows are remembered
+// as one bit per row in a per-column bitmap (16 rows per word).  A lane
+// without a pending row advances its envelope's owner with the sweep, so its
+// live window stays small.
+template <bool SMALL, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_env_lane_epi(EnvArgs a, int hb)
+{
+    constexpr int C = 32;
+    __shared__ uint32_t ring[WPB * C * 64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint32_t* const rl = ring + wv * C * 64 + lane;
+    const int n = (int)a.nz;
+    const int64_t stride = a.nx * a.ny;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    const uint32_t hm = (1u << hb) - 1u;
+    const uint64_t ngroups = (a.ntiles + WPB - 1) / WPB;
+    const int NONE = n;
+#define SLOT(k) (((k) & (C - 1)) * 64)
+
+    for (uint64_t t = blockIdx.x; t < ngroups; t += gridDim.x) {
+        const uint64_t tile = xcd_remap(t, ngroups) * WPB + wv;
+        if (tile >= a.ntiles)
+            continue;
+        const int64_t xb = (int64_t)(tile % (uint64_t)nxb), o = (int64_t)(tile / (uint64_t)nxb);
+        const int64_t x0 = xb * 64;
+        const bool valid = x0 + lane < a.nx;
+        const int64_t tb = o * a.nx + x0;
+        const uint32_t* __restrict__ inb = a.win + tb;
+        const uint32_t* __restrict__ w1b = a.w1 + tb;
+        const float* xqb = a.xq + tb;       // may alias ob (in place)
+        uint32_t* const w2b = a.w + tb;
+        float* const ob = a.out + tb;
+        uint16_t* const nb = a.need + tb;
+        const uint32_t us = (uint32_t)stride;
+        const uint32_t uc = valid ? (uint32_t)lane : 0u;
+        const float eta_eb = a.eta_eb, power = a.power;
+
+        int lo = 0, top = -1;
+        int e = NONE;                       // oldest needed row not yet emitted
+        uint32_t be = 0xFFFFFFFFu;          // envelope value at row e over the sites read so far
+        float xe = 0.0f;                    // x' at row e
+        uint32_t w1e = QAI_WORD_INF;        // first-EDT word at row e
+        uint32_t f0g = 0, f1g = 0, t0g = 0, t1g = 0, f2p = 0, t2p = 0;
+        int f0h = 0, f1h = 0, t0h = 0, t1h = 0;
+        bool ovf = false;
+        uint32_t cur16 = 0u;                // needed bits of the current block of 16 rows
+
+        auto front_to = [&](int r) {
+            if (top < lo)
+                return;
+            uint32_t a0 = f0g + sq24(r - f0h);
+            if (lo < top) {
+                uint32_t a1 = f1g + sq24(r - f1h);
+                if (a1 < a0) {
+                    ++lo;
+                    f0g = f1g; f0h = f1h; a0 = a1;
+                    f1g = f2p >> hb; f1h = (int)(f2p & hm);
+                    f2p = rl[SLOT(lo + 2)];
+#pragma unroll 1
+                    for (int it = 0; it < C && lo < top; ++it) {
+                        a1 = f1g + sq24(r - f1h);
+                        if (!(a1 < a0))
+                            break;
+                        ++lo;
+                        f0g = f1g; f0h = f1h; a0 = a1;
+                        f1g = f2p >> hb; f1h = (int)(f2p & hm);
+                        f2p = rl[SLOT(lo + 2)];
+                    }
+                }
+            }
+            be = a0;
+        };
+
+        // first needed row >= r among the rows read so far (<= i), else NONE
+        auto next_needed = [&](int r, int i) -> int {
+#pragma unroll 1
+            for (int k = r >> 4; k <= (i >> 4); ++k) {
+                uint32_t bits = (k == (i >> 4)) ? cur16 : (uint32_t)nb[(uint32_t)k * us + uc];
+                if (k == (r >> 4))
+                    bits &= 0xFFFFu << (r & 15);
+                if (bits)
+                    return k * 16 + __builtin_ctz(bits);
+            }
+            return NONE;
+        };
+
+        // emit the pending row: out and the distance word, then take the next one
+        auto emit = [&](int i, bool has_b2) {
+            const int se = word_sign(w1e);
+            const float wt = idw_weight(word_d2(w1e), false, has_b2 ? be : 0u, !has_b2, power);
+            ob[(uint32_t)e * us + uc] = fmaf(wt, (float)se * eta_eb, xe);
+            w2b[(uint32_t)e * us + uc] = has_b2 ? (be << 2) : QAI_WORD_INF;
+            e = next_needed(e + 1, i);
+            if (e != NONE) {
+                xe = xqb[(uint32_t)e * us + uc];
+                w1e = w1b[(uint32_t)e * us + uc];
+                front_to(e);
+            }
+        };
+
+        auto row_step = [&](int i, uint32_t w, float xv, uint32_t wv1) {
+            if (w != QAI_WORD_INF && !ovf) {
+                const uint32_t g = w >> 2;
+                if (top > lo && remove_sel<SMALL>(t1g, t0g, g, t1h, t0h, i)) {
+                    --top;
+                    t0g = t1g; t0h = t1h;
+                    t1g = t2p >> hb; t1h = (int)(t2p & hm);
+                    t2p = rl[SLOT(top - 2)];
+#pragma unroll 1
+                    for (int it = 0; it < C && top > lo; ++it) {
+                        if (!remove_sel<SMALL>(t1g, t0g, g, t1h, t0h, i))
+                            break;
+                        --top;
+                        t0g = t1g; t0h = t1h;
+                        t1g = t2p >> hb; t1h = (int)(t2p & hm);
+                        t2p = rl[SLOT(top - 2)];
+                    }
+                }
+                if (top - lo + 1 >= C) {
+                    ovf = true;
+                } else {
+                    ++top;
+                    const uint32_t pk = (g << hb) | (uint32_t)i;
+                    rl[SLOT(top)] = pk;
+                    t2p = (t1g << hb) | (uint32_t)t1h;
+                    t1g = t0g; t1h = t0h; t0g = g; t0h = i;
+                    const uint32_t vi = g + sq24((e < NONE ? e : i) - i);
+                    if (top == lo) {
+                        f0g = g; f0h = i; be = vi;
+                    } else {
+                        if (top == lo + 1) { f1g = g; f1h = i; }
+                        if (top == lo + 2) f2p = pk;
+                        be = min(be, vi);
+                    }
+                }
+            }
+            // step E where it does not depend on the distance to B2
+            const int s = word_sign(wv1);
+            const bool need = s != 0 && wv1 != QAI_WORD_INF && word_d2(wv1) != 0u;
+            if ((i & 15) == 0)
+                cur16 = 0u;
+            cur16 |= (need ? 1u : 0u) << (i & 15);
+            ob[(uint32_t)i * us + uc] = (s == 0 || need) ? xv : fmaf(1.0f, (float)s * eta_eb, xv);
+            if ((i & 15) == 15 || i == n - 1)
+                nb[(uint32_t)(i >> 4) * us + uc] = (uint16_t)cur16;
+            if (need && e == NONE) {
+                e = i;
+                xe = xv;
+                w1e = wv1;
+                front_to(e);
+            }
+            const bool fin = !ovf && e <= i && top >= lo && be <= sq24(i + 1 - e);
+            if (fin)
+                emit(i, true);
+            if (!ovf && e == NONE)
+                front_to(i + 1); // no pending row: the owner follows the sweep
+        };
+
+        auto catch_up = [&](int i) {
+#pragma unroll 1
+            for (int it = 0; it < n; ++it) {
+                const bool fin = !ovf && top - lo + 1 > C - 9 && e <= i && be <= sq24(i + 1 - e);
+                if (__ballot(fin) == 0ull)
+                    break;
+                if (fin)
+                    emit(i, true);
+            }
+        };
+
+        uint32_t A[8], B[8], WA[8], WB[8];
+        float XA[8], XB[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t off = (uint32_t)min(k, n - 1) * us + uc;
+            A[k] = inb[off];
+            XA[k] = xqb[off];
+            WA[k] = w1b[off];
+        }
+        for (int i0 = 0; i0 < n; i0 += 16) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t off = (uint32_t)min(i0 + 8 + k, n - 1) * us + uc;
+                B[k] = inb[off];
+                XB[k] = xqb[off];
+                WB[k] = w1b[off];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (i0 + k < n)
+                    row_step(i0 + k, A[k], XA[k], WA[k]);
+            catch_up(min(i0 + 7, n - 1));
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t off = (uint32_t)min(i0 + 16 + k, n - 1) * us + uc;
+                A[k] = inb[off];
+                XA[k] = xqb[off];
+                WA[k] = w1b[off];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (i0 + 8 + k < n)
+                    row_step(i0 + 8 + k, B[k], XB[k], WB[k]);
+            catch_up(min(i0 + 15, n - 1));
+        }
+        // every pending row is final now
+#pragma unroll 1
+        for (int it = 0; it < n; ++it) {
+            const bool more = !ovf && e < NONE;
+            if (__ballot(more) == 0ull)
+                break;
+            if (more)
+                emit(n - 1, top >= lo);
+        }
+#undef SLOT
+
+        // columns whose live window outgrew the ring: exact outward search at
+        // their needed rows from the pending one on (rows before it are done,
+        // and the rows from it on still hold x', also when out aliases x'),
+        // one column at a time by the whole wave
+        uint64_t om = __ballot(ovf && valid);
+        while (om) {
+            const int l = __ffsll((unsigned long long)om) - 1;
+            om &= om - 1ull;
+            const int e0 = __shfl(e, l);
+            for (int p = e0 + lane; p < n; p += 64) {
+                const uint32_t wv1 = w1b[(int64_t)p * stride + l];
+                const int s = word_sign(wv1);
+                if (!(s != 0 && wv1 != QAI_WORD_INF && word_d2(wv1) != 0u))
+                    continue;
+                uint32_t best = inb[(int64_t)p * stride + l];
+                for (int r = 1; r < n; ++r) {
+                    const uint32_t r2 = (uint32_t)r * (uint32_t)r << 2;
+                    if (r2 > (best | 3u))
+                        break;
+                    const int l0 = p - r, h0 = p + r;
+                    if (l0 < 0 && h0 >= n)
+                        break;
+                    if (l0 >= 0) {
+                        const uint32_t cand = word_add(inb[(int64_t)l0 * stride + l], r2);
+                        if ((cand >> 2) <= (best >> 2))
+                            best = cand;
+                    }
+                    if (h0 < n) {
+                        const uint32_t cand = word_add(inb[(int64_t)h0 * stride + l], r2);
+                        if ((cand >> 2) < (best >> 2))
+                            best = cand;
+                    }
+                }
+                const bool none2 = best == QAI_WORD_INF;
+                const float wt = idw_weight(word_d2(wv1), false, none2 ? 0u : word_d2(best), none2, power);
+                ob[(int64_t)p * stride + l] = fmaf(wt, (float)s * eta_eb, xqb[(int64_t)p * stride + l]);
+                w2b[(int64_t)p * stride + l] = best;
+            }
+        }
+    }
+}
+
 __global__ void k_clear(uint32_t* p, int n)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1738,6 +2003,20 @@ static hipError_t launch_swin_t(EnvArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
+static hipError_t launch_lane_epi(EnvArgs a, int hb, bool small, hipStream_t s)
+{
+    constexpr int WPB = 4;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    a.ntiles = (uint64_t)(nxb * a.ny);
+    const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
+    const dim3 grid(grid_cap(groups, 1u << 20)), blk(64 * WPB);
+    if (small)
+        hipLaunchKernelGGL((k_env_lane_epi<true, WPB>), grid, blk, 0, s, a, hb);
+    else
+        hipLaunchKernelGGL((k_env_lane_epi<false, WPB>), grid, blk, 0, s, a, hb);
+    return hipGetLastError();
+}
+
 hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_t s)
 {
     const int64_t n = axis == 1 ? a.ny : a.nz;
@@ -1916,6 +2195,29 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         QAI_TRY(launch_env(1, false, ea, t, s));
         prof_end(s);
         c2 = nx2;
+    }
+    const qai_taps& tp = p.taps;
+    const bool any_tap = tp.q || tp.b1 || tp.sb || tp.s || tp.d1sq || tp.b2 || tp.d2sq || tp.w;
+    int hb = 0;
+    bool small = false;
+    if (p.nz > 1 && !any_tap && p.need && t.env_algo[2] == 3 && lane_geometry(2, ea, hb, small)) {
+        // last pass of step D fused with step E
+        const int nx2 = (c2 == o0) ? o1 : o0;
+        EnvArgs ez = ea;
+        ez.win = buf[c2];
+        ez.w = buf[nx2];
+        ez.w1 = buf[w1];
+        ez.xq = p.xq;
+        ez.out = p.out;
+        ez.eta_eb = p.eta * p.eb;
+        ez.power = p.power;
+        ez.need = p.need;
+        prof_begin("edt2_z_interp", s);
+        QAI_TRY(launch_lane_epi(ez, hb, small, s));
+        prof_end(s);
+        p.w1_final = buf[w1];
+        p.w2_final = buf[nx2];
+        return hipSuccess;
     }
     if (p.nz > 1) {
         const int nx2 = (c2 == o0) ? o1 : o0;

@@ -18,12 +18,17 @@ KEYS = ("q", "b1", "sb", "s", "d1sq", "b2", "d2sq")
 
 
 def gpu_run(xq, eb, eta=0.9, power=1.0):
+    """Both forms of the call: with every tap (all passes written out) and
+    without (the last EDT pass fused with step E); the outputs must agree
+    bit for bit."""
     import paper_2602_20097_amd as qai
     t = torch.from_numpy(np.ascontiguousarray(xq, np.float32)).cuda()
     out, taps = qai.mitigate(t, eb, eta, power, taps=True)
+    plain = qai.mitigate(t, eb, eta, power)
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in taps.items()}
     res["out"] = out.cpu().numpy()
+    res["out_plain"] = plain.cpu().numpy()
     return res
 
 
@@ -37,6 +42,7 @@ def assert_parity(xq, eb, eta=0.9, power=1.0, label=""):
             bad = np.argwhere(a.astype(np.int64) != b.astype(np.int64))
             raise AssertionError(f"{label}: tap {k} differs at {len(bad)} voxels, first {bad[:5].tolist()}: "
                                  f"gpu {a[tuple(bad[0])]} oracle {b[tuple(bad[0])]}")
+    assert np.array_equal(g["out_plain"].view(np.uint32), g["out"].view(np.uint32)), f"{label}: fused path differs"
     err = np.abs(g["out"].astype(np.float64) - r["out"])
     lim = REL_TOL * np.maximum(np.abs(r["out"]), eb)
     assert (err <= lim).all(), f"{label}: out off by {err.max():.3g} (limit {lim[np.argmax(err - lim)]:.3g})"
