@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 STAGES = [
     (r"k_seed_(reg|slab|xscan)<0", "seed1_xscan"),
     (r"k_seed_(reg|slab|xscan)<1", "seed2_xscan"),
+    (r"k_env_lane_epi", "edt2_z_interp"),
     (r"k_interp", "interp"),
     (r"k_copy", "copy_probe"),
     (r"k_clear", "clear"),
