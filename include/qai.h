@@ -194,7 +194,8 @@ typedef struct qai_tuning {
     int32_t tile_log2[2];  /* log2 of x-columns per tile of the tiled variants, y and z (-1: auto) */
     int32_t seed_rows;     /* x-lines (wavefronts) per workgroup of the LDS-slab seed passes
                               (1..8); 0 selects the register-resident variant (8 lines per
-                              workgroup) wherever x-lines hold at most 512 voxels */
+                              workgroup) wherever x-lines hold at most 512 voxels; -1 the
+                              line-per-wave variant (neighbour lines read through the caches) */
     int32_t seed_planes;   /* z-planes marched per workgroup of the seed passes (>= 1) */
     int32_t window_threads; /* threads per workgroup of the windowed variant (64..1024) */
 } qai_tuning;

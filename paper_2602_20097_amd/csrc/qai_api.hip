@@ -385,8 +385,8 @@ int qai_tuning_set(const qai_tuning* in)
         for (int r : {in->edt1_ring, in->edt2_ring})
             if (r != 16 && r != 32 && r != 64)
                 return fail(QAI_EINVAL, "ring sizes must be 16, 32 or 64");
-        if (in->seed_rows < 0 || in->seed_rows > 8 || in->seed_planes < 1 || in->seed_planes > 4096)
-            return fail(QAI_EINVAL, "seed_rows must be in [0, 8] and seed_planes in [1, 4096]");
+        if (in->seed_rows < -1 || in->seed_rows > 8 || in->seed_planes < 1 || in->seed_planes > 4096)
+            return fail(QAI_EINVAL, "seed_rows must be in [-1, 8] and seed_planes in [1, 4096]");
         if (in->window_threads < 64 || in->window_threads > 1024 || in->window_threads % 64)
             return fail(QAI_EINVAL, "window_threads must be a multiple of 64 in [64, 1024]");
         for (int a = 1; a <= 2; ++a) {

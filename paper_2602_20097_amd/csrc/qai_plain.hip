@@ -1837,6 +1837,8 @@ static hipError_t launch_seed_reg(const SeedArgs& in, int tz, hipStream_t s)
 
 hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s, int want_ty, int want_tz)
 {
+    if (want_ty < 0)
+        return launch_seed_lines(mode, in, s); // one x-line per wave, neighbours through the caches
     if (in.nx <= 512 && want_ty <= 0) {
         const int tz = in.nz > 1 ? (want_tz > 0 ? want_tz : 16) : 1;
         return mode == 0 ? launch_seed_reg<0>(in, tz, s) : launch_seed_reg<1>(in, tz, s);

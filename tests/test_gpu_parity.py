@@ -173,7 +173,7 @@ def test_every_pass_algorithm_gives_the_same_transform():
     try:
         for xq, eb in cases:
             r = oracle.qai(xq, eb)
-            combos = [(a1, a2, 0) for a1 in (0, 1, 2, 4) for a2 in (0, 1, 2, 3, 4)] + [(4, 3, 4), (4, 3, 1)]
+            combos = [(a1, a2, 0) for a1 in (0, 1, 2, 4) for a2 in (0, 1, 2, 3, 4)] + [(4, 3, 4), (4, 3, 1), (4, 3, -1)]
             for a1, a2, rows in combos:
                 qai.set_tuning(edt1_algo=[a1, a1], edt2_algo=[a2, a2], seed_rows=rows)
                 print(f"tuning edt1 {a1} edt2 {a2} seed_rows {rows} shape {xq.shape}", flush=True)
