@@ -93,8 +93,8 @@ int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out
 
 /* Bytes of device workspace qai_mitigate_ex needs for dims: a 64 KiB header
  * (status word, reduction partials), three 32-bit words per voxel (the packed
- * distance words of the passes, ping-ponged) and one bit per voxel (16-bit
- * words per 16 z-rows of each column, used by the fused final pass), each part
+ * distance words of the passes, ping-ponged) and one bit per voxel (flags of
+ * the fused final pass: 128 bytes per 1024 voxels, rounded up), each part
  * rounded up to 256 bytes.  0 for invalid dims. */
 size_t qai_workspace_bytes(const int64_t dims[3]);
 
@@ -188,7 +188,10 @@ typedef struct qai_tuning {
     int32_t edt2_algo[2];  /* the same for the second EDT, plus 3: per-lane online envelope
                               (payload-free words; falls back to 0 where its packed ring
                               entries would not fit 32 bits); -1 (the default) picks 1 below
-                              1024 tiles, else 3 */
+                              1024 tiles, else 3.  For the z pass of a 3-D call without taps
+                              (16-byte aligned field and out), -1 computes the distance to B2
+                              only where step E needs it, by an exact outward search along z
+                              fused with step E; an explicit choice runs the whole pass */
     int32_t edt1_ring;     /* live-window ring entries of the streaming envelope: 16, 32 or 64 */
     int32_t edt2_ring;
     int32_t tile_log2[2];  /* log2 of x-columns per tile of the tiled variants, y and z (-1: auto) */

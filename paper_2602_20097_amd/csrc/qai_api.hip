@@ -152,7 +152,7 @@ void ws_buffers(void* ws, int64_t n, Plan1& p)
     p.bufA = word_buffer(ws, n, 0);
     p.bufB = word_buffer(ws, n, 1);
     p.bufC = word_buffer(ws, n, 2);
-    p.need = (uint16_t*)word_buffer(ws, n, 3);
+    p.flags = (uint64_t*)word_buffer(ws, n, 3);
 }
 
 int tuning_to_abi(const Tuning& t, qai_tuning* out)
@@ -256,9 +256,8 @@ size_t qai_workspace_bytes(const int64_t dims[3])
         if (dims[a] < 1 || dims[a] > QAI_MAX_EXTENT)
             return 0;
     n = dims[0] * dims[1] * dims[2];
-    // three word buffers, then the fused final pass's bitmap: ceil(nz/16) x ny x nx 16-bit words
-    const size_t bits = (size_t)((dims[0] + 15) / 16) * (size_t)dims[1] * (size_t)dims[2] * 2;
-    return kHeaderBytes + 3 * align256((size_t)n * 4) + align256(bits);
+    // three word buffers, then the fused final pass's flag words
+    return kHeaderBytes + 3 * align256((size_t)n * 4) + align256(qai::flag_bytes(n));
 }
 
 int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const qai_params* params, void* ws,

@@ -45,7 +45,6 @@ struct EnvArgs {
     float eta_eb, power;
     int32_t* td2;
     float* tw;
-    uint16_t* need;       // fused final pass: per column, one bit per row of "step E needs d2 here"
 };
 
 struct InterpArgs {
@@ -91,12 +90,16 @@ struct Plan1 {
     uint32_t* bufB;
     uint32_t* bufC;
     uint32_t* status;
-    uint16_t* need;       // scratch bitmap of the fused final pass (N/16 words)
+    uint64_t* flags;      // fused final pass: one bit per voxel, see flag_bytes
     qai_taps taps;
     const uint32_t* w1_final;
     const uint32_t* w2_final;
 };
 hipError_t run_plain(Plan1& p, const Tuning& t, hipStream_t s);
+
+// Bytes of the fused final pass's flag words for n voxels: one 64-bit word
+// per 64 voxels, in blocks of 1024 voxels.
+inline size_t flag_bytes(int64_t n) { return (size_t)((n + 1023) / 1024) * 128; }
 
 // Stage-timing hooks (active when profiling is enabled).
 void prof_begin(const char* name, hipStream_t s);

@@ -15,6 +15,7 @@
 // All kernels are memory bound: no dense contraction exists on this path.
 #include "qai_device.h"
 #include "qai_kernels.h"
+#include <type_traits>
 
 namespace qai {
 
@@ -617,6 +618,267 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x)
         interp_store(i, a.w2[i], a.w1, a.xq, a.out, a.eta_eb, a.power, a.td2, a.tw);
+}
+
+// Step E over a 3-D field with the last pass of step D done only where the
+// weight needs the distance to B2: S != 0 off B1 ("needed" voxels).  There
+// d2 = min over z' of G(z') + (z - z')^2 with G the result of the y pass;
+// everywhere else out = x' (S = 0) or x' + S eta eb (on B1), exactly as
+// interp_store computes them.  Two phases:
+//   k_interp_own   streams w1 and x' (four voxels per thread, 16-byte
+//                  accesses) and writes out.  At a needed voxel it reads
+//                  G(z) itself: G(z) = 0 means the voxel is on B2 (w = 0) and
+//                  is finished; otherwise out keeps x' for now and the voxel
+//                  is flagged: per wave, four 64-bit ballots (one per voxel
+//                  slot of a thread), always written, so the flags need no
+//                  clearing.
+//   k_interp_far   one thread per ballot word: for each flagged voxel, an
+//                  exact outward search along z (stop once r^2 exceeds the
+//                  best value: every candidate at offset r adds at least r^2),
+//                  four offsets per round, then out and the distance word.
+// Needed voxels far from B2 are few but their searches are long; keeping
+// them out of the streaming waves keeps those waves short.  The distance word
+// of every needed voxel goes to w2 (the adjoint reads it there).
+struct ZsArgs {
+    const uint32_t* w1;   // first-EDT words
+    const uint32_t* gy;   // second EDT after its y pass
+    uint32_t* w2;         // distance words at needed voxels
+    const float* xq;      // may alias out
+    float* out;
+    uint64_t* flags;      // four ballot words per wave of k_interp_own
+    int64_t nx, ny, nz;
+    float eta_eb, power;
+};
+
+// Loads of the y-pass words by 32-bit byte offset (buffer loads, fields below
+// 2^30 voxels) or by 64-bit index.
+template <bool BUF>
+struct GyReader {
+    const uint32_t* gy;
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ __forceinline__ GyReader(const uint32_t* p, int64_t n)
+        : gy(p), rs(__builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(p), (short)0, BUF ? (int)(n * 4) : 0, 0x00020000))
+    {
+    }
+    // word at voxel index i (byte offset o = 4 i when BUF)
+    __device__ __forceinline__ uint32_t at(int64_t i) const
+    {
+        if (BUF)
+            return __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)i * 4u, 0, 0);
+        return gy[i];
+    }
+};
+
+// Exact d2 at voxel i (plane z) from the y-pass words: the outward search
+// stops once r^2 exceeds the best value (every candidate at offset r adds at
+// least r^2).  Each round issues all its loads before using any.  QAI_WORD_INF when the column holds no site.
+template <bool BUF>
+__device__ __forceinline__ uint32_t zsearch(const GyReader<BUF>& g, int64_t i, int64_t plane, int z, int nz)
+{
+    const uint32_t g0 = g.at(i);
+    uint32_t best = (g0 == QAI_WORD_INF) ? QAI_WORD_INF : (g0 >> 2);
+    auto round = [&](auto rc, int r0) {
+        constexpr int R = decltype(rc)::value;
+        uint32_t lo[R], hi[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int r = r0 + k;
+            lo[k] = (z - r >= 0) ? g.at(i - (int64_t)r * plane) : QAI_WORD_INF;
+            hi[k] = (z + r < nz) ? g.at(i + (int64_t)r * plane) : QAI_WORD_INF;
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const uint32_t r2 = (uint32_t)((r0 + k) * (r0 + k));
+            if (lo[k] != QAI_WORD_INF)
+                best = min(best, (lo[k] >> 2) + r2);
+            if (hi[k] != QAI_WORD_INF)
+                best = min(best, (hi[k] >> 2) + r2);
+        }
+    };
+    // offsets 1-4, 5-8, 9-16, 17-32, then 32 at a time: at most twice the
+    // loads of a one-offset-per-round search, in a handful of round trips
+#pragma unroll 1
+    for (int r0 = 1; r0 < nz;) {
+        if ((best != QAI_WORD_INF && (uint32_t)(r0 * r0) > best) || (z - r0 < 0 && z + r0 >= nz))
+            break;
+        if (r0 < 9) {
+            round(std::integral_constant<int, 4>(), r0);
+            r0 += 4;
+        } else if (r0 < 17) {
+            round(std::integral_constant<int, 8>(), r0);
+            r0 += 8;
+        } else if (r0 < 33) {
+            round(std::integral_constant<int, 16>(), r0);
+            r0 += 16;
+        } else {
+            round(std::integral_constant<int, 32>(), r0);
+            r0 += 32;
+        }
+    }
+    return best;
+}
+
+// out at a needed voxel from its distance value d2 (QAI_WORD_INF: no B2)
+__device__ __forceinline__ float interp_at(const ZsArgs& a, int64_t i, uint32_t w1w, float xv, uint32_t d2)
+{
+    const bool none2 = d2 == QAI_WORD_INF;
+    a.w2[i] = none2 ? QAI_WORD_INF : (d2 << 2);
+    const float wt = idw_weight(word_d2(w1w), false, none2 ? 0u : d2, none2, a.power);
+    return fmaf(wt, (float)word_sign(w1w) * a.eta_eb, xv);
+}
+
+// step E where the weight does not need the search; false where it does (out
+// then keeps x' for the second phase)
+__device__ __forceinline__ bool interp_near(const ZsArgs& a, int64_t i, uint32_t w, float x, uint32_t g, float& o)
+{
+    const int s = word_sign(w);
+    if (s == 0) {
+        o = x;
+    } else if (word_d2(w) == 0u) {
+        o = fmaf(1.0f, (float)s * a.eta_eb, x); // on B1: w = 1
+    } else if (g == 0u) {
+        o = interp_at(a, i, w, x, 0u);          // on B2: w = 0
+    } else {
+        o = x;
+        return false;
+    }
+    return true;
+}
+
+template <bool BUF>
+__global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
+{
+    const int64_t n = a.nx * a.ny * a.nz;
+    const GyReader<BUF> g(a.gy, n);
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    bool far[4] = {false, false, false, false};
+    uint32_t w[4];
+    float x[4], o[4];
+    if (i0 + 4 <= n) {
+        const uint4 wq = *reinterpret_cast<const uint4*>(a.w1 + i0);
+        const float4 xq4 = *reinterpret_cast<const float4*>(a.xq + i0);
+        w[0] = wq.x; w[1] = wq.y; w[2] = wq.z; w[3] = wq.w;
+        x[0] = xq4.x; x[1] = xq4.y; x[2] = xq4.z; x[3] = xq4.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            w[k] = i0 + k < n ? a.w1[i0 + k] : 0u; // beyond the field: S = 0, nothing done
+            x[k] = i0 + k < n ? a.xq[i0 + k] : 0.0f;
+        }
+    }
+    uint32_t gv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        gv[k] = (word_sign(w[k]) != 0 && word_d2(w[k]) != 0u) ? g.at(i0 + k) : QAI_WORD_INF;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        far[k] = !interp_near(a, i0 + k, w[k], x[k], gv[k], o[k]);
+    if (i0 + 4 <= n) {
+        *reinterpret_cast<float4*>(a.out + i0) = make_float4(o[0], o[1], o[2], o[3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + k < n)
+                a.out[i0 + k] = o[k];
+    }
+    const uint64_t m0 = __ballot(far[0]), m1 = __ballot(far[1]), m2 = __ballot(far[2]), m3 = __ballot(far[3]);
+    const int lane = threadIdx.x & 63;
+    if (lane < 4) {
+        const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+        a.flags[wave * 4 + lane] = lane == 0 ? m0 : (lane == 1 ? m1 : (lane == 2 ? m2 : m3));
+    }
+}
+
+// A block takes the four flag words of 64 waves of k_interp_own, spaced
+// gridDim.x waves apart: flagged voxels gather in places (along B2, and on
+// the two z faces, where B2 never lies, nearly every needed voxel is
+// flagged), and the spacing spreads such places over many blocks.  The
+// block's flagged voxels are listed in LDS (block-wide prefix sum of the word
+// popcounts) and dealt one per thread; lists longer than the LDS window go in
+// several rounds.
+template <bool BUF>
+__global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords)
+{
+    constexpr int L = 1024;
+    __shared__ int64_t list[L];
+    __shared__ int wsum[4];
+    const int64_t plane = a.nx * a.ny;
+    const GyReader<BUF> g(a.gy, plane * a.nz);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t grp = (int64_t)blockIdx.x + (int64_t)(tid >> 2) * gridDim.x; // wave of k_interp_own
+    const int64_t wi = grp * 4 + (tid & 3);
+    const uint64_t m = wi < nwords ? a.flags[wi] : 0ull;
+    const int c = __popcll(m);
+    // exclusive prefix of c over the block
+    int incl = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d)
+            incl += v;
+    }
+    if (lane == 63)
+        wsum[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        before += k < wv ? wsum[k] : 0;
+        total += wsum[k];
+    }
+    const int off = before + incl - c;
+    const int64_t base = (wi >> 2) * 256 + (wi & 3); // voxel of bit l: base + 4 l
+#pragma unroll 1
+    for (int w0 = 0; w0 < total; w0 += L) {
+        // this thread's flagged voxels that fall in list window [w0, w0 + L)
+        if (off < w0 + L && off + c > w0) {
+            uint64_t mm = m;
+            int p = off;
+            while (mm) {
+                const int l = __ffsll((unsigned long long)mm) - 1;
+                mm &= mm - 1ull;
+                if (p >= w0 && p < w0 + L)
+                    list[p - w0] = base + 4 * (int64_t)l;
+                ++p;
+            }
+        }
+        __syncthreads();
+        const int cnt = min(L, total - w0);
+#pragma unroll 1
+        for (int j = tid; j < cnt; j += 256) {
+            const int64_t i = list[j];
+            const uint32_t w = a.w1[i];
+            const float xv = a.xq[i];
+            const uint32_t d2 = zsearch<BUF>(g, i, plane, (int)(i / plane), (int)a.nz);
+            a.out[i] = interp_at(a, i, w, xv, d2);
+        }
+        __syncthreads();
+    }
+}
+
+static hipError_t launch_interp_search(const ZsArgs& a, hipStream_t s)
+{
+    const int64_t n = a.nx * a.ny * a.nz;
+    if ((((uintptr_t)a.w1 | (uintptr_t)a.xq | (uintptr_t)a.out) & 15u) != 0)
+        return hipErrorInvalidValue; // the caller takes the unfused path instead
+    const int64_t blocks = (n + 1023) / 1024;
+    if (blocks > 0x7FFFFFFF)
+        return hipErrorInvalidValue;
+    const bool buf = n < ((int64_t)1 << 29);
+    if (buf)
+        hipLaunchKernelGGL(k_interp_own<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_interp_own<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int64_t nwords = blocks * 16; // flag_bytes(n) / 8
+    const dim3 grid((unsigned)((nwords / 4 + 63) / 64));
+    if (buf)
+        hipLaunchKernelGGL(k_interp_far<true>, grid, dim3(256), 0, s, a, nwords);
+    else
+        hipLaunchKernelGGL(k_interp_far<false>, grid, dim3(256), 0, s, a, nwords);
+    return hipGetLastError();
 }
 
 // --------------------------------------------------------- envelope pass
@@ -1408,27 +1670,35 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane(EnvArgs a, int hb)
             }
         };
 
+        // Full blocks of 16 rows, then the ragged tail.  Every prefetched word
+        // is consumed before the catch-up loops, so no load is pending at
+        // their entry (a loop with stores entered with a pending load costs a
+        // wait for every outstanding memory operation).
+        const int nfull = n & ~15;
         uint32_t A[8], B[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             A[k] = inb[(uint32_t)min(k, n - 1) * us + uc];
-        for (int i0 = 0; i0 < n; i0 += 16) {
+        for (int i0 = 0; i0 < nfull; i0 += 16) {
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                B[k] = inb[(uint32_t)min(i0 + 8 + k, n - 1) * us + uc];
+                B[k] = inb[(uint32_t)(i0 + 8 + k) * us + uc];
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                if (i0 + k < n)
-                    row_step(i0 + k, A[k]);
-            catch_up(min(i0 + 7, n - 1));
+                row_step(i0 + k, A[k]);
+            catch_up(i0 + 7);
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 A[k] = inb[(uint32_t)min(i0 + 16 + k, n - 1) * us + uc];
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                if (i0 + 8 + k < n)
-                    row_step(i0 + 8 + k, B[k]);
-            catch_up(min(i0 + 15, n - 1));
+                row_step(i0 + 8 + k, B[k]);
+            catch_up(i0 + 15);
+        }
+#pragma unroll 1
+        for (int i = nfull; i < n; ++i) {
+            row_step(i, inb[(uint32_t)i * us + uc]);
+            catch_up(i);
         }
         // every row left is final
 #pragma unroll 1
@@ -1472,271 +1742,6 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane(EnvArgs a, int hb)
                     }
                 }
                 outb[(int64_t)p * stride + l] = best;
-            }
-        }
-    }
-}
-
-// The second EDT's last pass (z) fused with step E.  The weight needs the
-// distance to B2 only where S != 0 off B1 ("needed" voxels); everywhere else
-// out = x' (S = 0) or x' + S eta eb (on B1, w = 1).  So every row's output is
-// written as the sweep reads it (needed rows provisionally with x'), and the
-// online envelope of k_env_lane emits only needed rows: the lane keeps its
-// oldest pending needed row e (with its x' and first-EDT word), and when e is
-// final it writes out[e] and the distance word of e (which the adjoint reads),
-// then moves e to the next needed row it has read.  Needed rows are remembered
-// as one bit per row in a per-column bitmap (16 rows per word).  A lane
-// without a pending row advances its envelope's owner with the sweep, so its
-// live window stays small.
-template <bool SMALL, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_env_lane_epi(EnvArgs a, int hb)
-{
-    constexpr int C = 32;
-    __shared__ uint32_t ring[WPB * C * 64];
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    uint32_t* const rl = ring + wv * C * 64 + lane;
-    const int n = (int)a.nz;
-    const int64_t stride = a.nx * a.ny;
-    const int64_t nxb = (a.nx + 63) >> 6;
-    const uint32_t hm = (1u << hb) - 1u;
-    const uint64_t ngroups = (a.ntiles + WPB - 1) / WPB;
-    const int NONE = n;
-#define SLOT(k) (((k) & (C - 1)) * 64)
-
-    for (uint64_t t = blockIdx.x; t < ngroups; t += gridDim.x) {
-        const uint64_t tile = xcd_remap(t, ngroups) * WPB + wv;
-        if (tile >= a.ntiles)
-            continue;
-        const int64_t xb = (int64_t)(tile % (uint64_t)nxb), o = (int64_t)(tile / (uint64_t)nxb);
-        const int64_t x0 = xb * 64;
-        const bool valid = x0 + lane < a.nx;
-        const int64_t tb = o * a.nx + x0;
-        const uint32_t* __restrict__ inb = a.win + tb;
-        const uint32_t* __restrict__ w1b = a.w1 + tb;
-        const float* xqb = a.xq + tb;       // may alias ob (in place)
-        uint32_t* const w2b = a.w + tb;
-        float* const ob = a.out + tb;
-        uint16_t* const nb = a.need + tb;
-        const uint32_t us = (uint32_t)stride;
-        const uint32_t uc = valid ? (uint32_t)lane : 0u;
-        const float eta_eb = a.eta_eb, power = a.power;
-
-        int lo = 0, top = -1;
-        int e = NONE;                       // oldest needed row not yet emitted
-        uint32_t be = 0xFFFFFFFFu;          // envelope value at row e over the sites read so far
-        float xe = 0.0f;                    // x' at row e
-        uint32_t w1e = QAI_WORD_INF;        // first-EDT word at row e
-        uint32_t f0g = 0, f1g = 0, t0g = 0, t1g = 0, f2p = 0, t2p = 0;
-        int f0h = 0, f1h = 0, t0h = 0, t1h = 0;
-        bool ovf = false;
-        uint32_t cur16 = 0u;                // needed bits of the current block of 16 rows
-
-        auto front_to = [&](int r) {
-            if (top < lo)
-                return;
-            uint32_t a0 = f0g + sq24(r - f0h);
-            if (lo < top) {
-                uint32_t a1 = f1g + sq24(r - f1h);
-                if (a1 < a0) {
-                    ++lo;
-                    f0g = f1g; f0h = f1h; a0 = a1;
-                    f1g = f2p >> hb; f1h = (int)(f2p & hm);
-                    f2p = rl[SLOT(lo + 2)];
-#pragma unroll 1
-                    for (int it = 0; it < C && lo < top; ++it) {
-                        a1 = f1g + sq24(r - f1h);
-                        if (!(a1 < a0))
-                            break;
-                        ++lo;
-                        f0g = f1g; f0h = f1h; a0 = a1;
-                        f1g = f2p >> hb; f1h = (int)(f2p & hm);
-                        f2p = rl[SLOT(lo + 2)];
-                    }
-                }
-            }
-            be = a0;
-        };
-
-        // first needed row >= r among the rows read so far (<= i), else NONE
-        auto next_needed = [&](int r, int i) -> int {
-#pragma unroll 1
-            for (int k = r >> 4; k <= (i >> 4); ++k) {
-                uint32_t bits = (k == (i >> 4)) ? cur16 : (uint32_t)nb[(uint32_t)k * us + uc];
-                if (k == (r >> 4))
-                    bits &= 0xFFFFu << (r & 15);
-                if (bits)
-                    return k * 16 + __builtin_ctz(bits);
-            }
-            return NONE;
-        };
-
-        // emit the pending row: out and the distance word, then take the next one
-        auto emit = [&](int i, bool has_b2) {
-            const int se = word_sign(w1e);
-            const float wt = idw_weight(word_d2(w1e), false, has_b2 ? be : 0u, !has_b2, power);
-            ob[(uint32_t)e * us + uc] = fmaf(wt, (float)se * eta_eb, xe);
-            w2b[(uint32_t)e * us + uc] = has_b2 ? (be << 2) : QAI_WORD_INF;
-            e = next_needed(e + 1, i);
-            if (e != NONE) {
-                xe = xqb[(uint32_t)e * us + uc];
-                w1e = w1b[(uint32_t)e * us + uc];
-                front_to(e);
-            }
-        };
-
-        auto row_step = [&](int i, uint32_t w, float xv, uint32_t wv1) {
-            if (w != QAI_WORD_INF && !ovf) {
-                const uint32_t g = w >> 2;
-                if (top > lo && remove_sel<SMALL>(t1g, t0g, g, t1h, t0h, i)) {
-                    --top;
-                    t0g = t1g; t0h = t1h;
-                    t1g = t2p >> hb; t1h = (int)(t2p & hm);
-                    t2p = rl[SLOT(top - 2)];
-#pragma unroll 1
-                    for (int it = 0; it < C && top > lo; ++it) {
-                        if (!remove_sel<SMALL>(t1g, t0g, g, t1h, t0h, i))
-                            break;
-                        --top;
-                        t0g = t1g; t0h = t1h;
-                        t1g = t2p >> hb; t1h = (int)(t2p & hm);
-                        t2p = rl[SLOT(top - 2)];
-                    }
-                }
-                if (top - lo + 1 >= C) {
-                    ovf = true;
-                } else {
-                    ++top;
-                    const uint32_t pk = (g << hb) | (uint32_t)i;
-                    rl[SLOT(top)] = pk;
-                    t2p = (t1g << hb) | (uint32_t)t1h;
-                    t1g = t0g; t1h = t0h; t0g = g; t0h = i;
-                    const uint32_t vi = g + sq24((e < NONE ? e : i) - i);
-                    if (top == lo) {
-                        f0g = g; f0h = i; be = vi;
-                    } else {
-                        if (top == lo + 1) { f1g = g; f1h = i; }
-                        if (top == lo + 2) f2p = pk;
-                        be = min(be, vi);
-                    }
-                }
-            }
-            // step E where it does not depend on the distance to B2
-            const int s = word_sign(wv1);
-            const bool need = s != 0 && wv1 != QAI_WORD_INF && word_d2(wv1) != 0u;
-            if ((i & 15) == 0)
-                cur16 = 0u;
-            cur16 |= (need ? 1u : 0u) << (i & 15);
-            ob[(uint32_t)i * us + uc] = (s == 0 || need) ? xv : fmaf(1.0f, (float)s * eta_eb, xv);
-            if ((i & 15) == 15 || i == n - 1)
-                nb[(uint32_t)(i >> 4) * us + uc] = (uint16_t)cur16;
-            if (need && e == NONE) {
-                e = i;
-                xe = xv;
-                w1e = wv1;
-                front_to(e);
-            }
-            const bool fin = !ovf && e <= i && top >= lo && be <= sq24(i + 1 - e);
-            if (fin)
-                emit(i, true);
-            if (!ovf && e == NONE)
-                front_to(i + 1); // no pending row: the owner follows the sweep
-        };
-
-        auto catch_up = [&](int i) {
-#pragma unroll 1
-            for (int it = 0; it < n; ++it) {
-                const bool fin = !ovf && top - lo + 1 > C - 9 && e <= i && be <= sq24(i + 1 - e);
-                if (__ballot(fin) == 0ull)
-                    break;
-                if (fin)
-                    emit(i, true);
-            }
-        };
-
-        uint32_t A[8], B[8], WA[8], WB[8];
-        float XA[8], XB[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t off = (uint32_t)min(k, n - 1) * us + uc;
-            A[k] = inb[off];
-            XA[k] = xqb[off];
-            WA[k] = w1b[off];
-        }
-        for (int i0 = 0; i0 < n; i0 += 16) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t off = (uint32_t)min(i0 + 8 + k, n - 1) * us + uc;
-                B[k] = inb[off];
-                XB[k] = xqb[off];
-                WB[k] = w1b[off];
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (i0 + k < n)
-                    row_step(i0 + k, A[k], XA[k], WA[k]);
-            catch_up(min(i0 + 7, n - 1));
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t off = (uint32_t)min(i0 + 16 + k, n - 1) * us + uc;
-                A[k] = inb[off];
-                XA[k] = xqb[off];
-                WA[k] = w1b[off];
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (i0 + 8 + k < n)
-                    row_step(i0 + 8 + k, B[k], XB[k], WB[k]);
-            catch_up(min(i0 + 15, n - 1));
-        }
-        // every pending row is final now
-#pragma unroll 1
-        for (int it = 0; it < n; ++it) {
-            const bool more = !ovf && e < NONE;
-            if (__ballot(more) == 0ull)
-                break;
-            if (more)
-                emit(n - 1, top >= lo);
-        }
-#undef SLOT
-
-        // columns whose live window outgrew the ring: exact outward search at
-        // their needed rows from the pending one on (rows before it are done,
-        // and the rows from it on still hold x', also when out aliases x'),
-        // one column at a time by the whole wave
-        uint64_t om = __ballot(ovf && valid);
-        while (om) {
-            const int l = __ffsll((unsigned long long)om) - 1;
-            om &= om - 1ull;
-            const int e0 = __shfl(e, l);
-            for (int p = e0 + lane; p < n; p += 64) {
-                const uint32_t wv1 = w1b[(int64_t)p * stride + l];
-                const int s = word_sign(wv1);
-                if (!(s != 0 && wv1 != QAI_WORD_INF && word_d2(wv1) != 0u))
-                    continue;
-                uint32_t best = inb[(int64_t)p * stride + l];
-                for (int r = 1; r < n; ++r) {
-                    const uint32_t r2 = (uint32_t)r * (uint32_t)r << 2;
-                    if (r2 > (best | 3u))
-                        break;
-                    const int l0 = p - r, h0 = p + r;
-                    if (l0 < 0 && h0 >= n)
-                        break;
-                    if (l0 >= 0) {
-                        const uint32_t cand = word_add(inb[(int64_t)l0 * stride + l], r2);
-                        if ((cand >> 2) <= (best >> 2))
-                            best = cand;
-                    }
-                    if (h0 < n) {
-                        const uint32_t cand = word_add(inb[(int64_t)h0 * stride + l], r2);
-                        if ((cand >> 2) < (best >> 2))
-                            best = cand;
-                    }
-                }
-                const bool none2 = best == QAI_WORD_INF;
-                const float wt = idw_weight(word_d2(wv1), false, none2 ? 0u : word_d2(best), none2, power);
-                ob[(int64_t)p * stride + l] = fmaf(wt, (float)s * eta_eb, xqb[(int64_t)p * stride + l]);
-                w2b[(int64_t)p * stride + l] = best;
             }
         }
     }
@@ -2005,20 +2010,6 @@ static hipError_t launch_swin_t(EnvArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
-static hipError_t launch_lane_epi(EnvArgs a, int hb, bool small, hipStream_t s)
-{
-    constexpr int WPB = 4;
-    const int64_t nxb = (a.nx + 63) >> 6;
-    a.ntiles = (uint64_t)(nxb * a.ny);
-    const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
-    const dim3 grid(grid_cap(groups, 1u << 20)), blk(64 * WPB);
-    if (small)
-        hipLaunchKernelGGL((k_env_lane_epi<true, WPB>), grid, blk, 0, s, a, hb);
-    else
-        hipLaunchKernelGGL((k_env_lane_epi<false, WPB>), grid, blk, 0, s, a, hb);
-    return hipGetLastError();
-}
-
 hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_t s)
 {
     const int64_t n = axis == 1 ? a.ny : a.nz;
@@ -2200,22 +2191,13 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
     }
     const qai_taps& tp = p.taps;
     const bool any_tap = tp.q || tp.b1 || tp.sb || tp.s || tp.d1sq || tp.b2 || tp.d2sq || tp.w;
-    int hb = 0;
-    bool small = false;
-    if (p.nz > 1 && !any_tap && p.need && t.env_algo[2] == 3 && lane_geometry(2, ea, hb, small)) {
-        // last pass of step D fused with step E
+    const bool aligned = (((uintptr_t)buf[w1] | (uintptr_t)p.xq | (uintptr_t)p.out) & 15u) == 0;
+    if (p.nz > 1 && !any_tap && t_in.env_algo[2] < 0 && p.flags && aligned) {
+        // last pass of step D only at needed voxels, fused with step E
         const int nx2 = (c2 == o0) ? o1 : o0;
-        EnvArgs ez = ea;
-        ez.win = buf[c2];
-        ez.w = buf[nx2];
-        ez.w1 = buf[w1];
-        ez.xq = p.xq;
-        ez.out = p.out;
-        ez.eta_eb = p.eta * p.eb;
-        ez.power = p.power;
-        ez.need = p.need;
+        ZsArgs za = {buf[w1], buf[c2], buf[nx2], p.xq, p.out, p.flags, p.nx, p.ny, p.nz, p.eta * p.eb, p.power};
         prof_begin("edt2_z_interp", s);
-        QAI_TRY(launch_lane_epi(ez, hb, small, s));
+        QAI_TRY(launch_interp_search(za, s));
         prof_end(s);
         p.w1_final = buf[w1];
         p.w2_final = buf[nx2];

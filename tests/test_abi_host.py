@@ -38,7 +38,7 @@ def test_workspace_bytes(lib):
         n = math.prod(shape)
         b = lib.qai_workspace_bytes(_lib.Dims(*shape))
         words = 3 * (((n * 4) + 255) // 256) * 256
-        bits = ((((shape[0] + 15) // 16) * shape[1] * shape[2] * 2 + 255) // 256) * 256
+        bits = (((n + 1023) // 1024 * 128 + 255) // 256) * 256
         assert b == 64 * 1024 + words + bits
     for bad in ((0, 4, 4), (4, -1, 4), (1, 1, 16385)):
         assert lib.qai_workspace_bytes(_lib.Dims(*bad)) == 0
