@@ -695,8 +695,7 @@ __device__ __forceinline__ uint32_t zsearch(const GyReader<BUF>& g, int64_t i, i
                 best = min(best, (hi[k] >> 2) + r2);
         }
     };
-    // offsets 1-4, 5-8, 9-16, 17-32, then 32 at a time: at most twice the
-    // loads of a one-offset-per-round search, in a handful of round trips
+    // offsets 1-4, 5-8, then 8 at a time
 #pragma unroll 1
     for (int r0 = 1; r0 < nz;) {
         if ((best != QAI_WORD_INF && (uint32_t)(r0 * r0) > best) || (z - r0 < 0 && z + r0 >= nz))
@@ -707,12 +706,9 @@ __device__ __forceinline__ uint32_t zsearch(const GyReader<BUF>& g, int64_t i, i
         } else if (r0 < 17) {
             round(std::integral_constant<int, 8>(), r0);
             r0 += 8;
-        } else if (r0 < 33) {
-            round(std::integral_constant<int, 16>(), r0);
-            r0 += 16;
         } else {
-            round(std::integral_constant<int, 32>(), r0);
-            r0 += 32;
+            round(std::integral_constant<int, 8>(), r0);
+            r0 += 8;
         }
     }
     return best;
@@ -1747,6 +1743,228 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane(EnvArgs a, int hb)
     }
 }
 
+// k_env_lane with stack entries kept as (c, h), c = g + h^2.  Maurer's
+// removal test for sites u < v < w (Section III-B) then reads
+//     (c_v - c_u)(h_w - h_v) - (c_w - c_v)(h_v - h_u) > 0,
+// the same integer as c g_v - b g_u - a g_w - a b c (expand c_k = g_k + h_k^2),
+// so with the differences of the top pair cached it costs two 24-bit
+// multiplies; "the next entry is strictly better at row r" reads
+// c_1 - c_0 < 2 r (h_1 - h_0).  A pop or a front step rebuilds its pair from
+// one packed ring entry (c << hb) | h.  Loads and stores use 32-bit byte
+// offsets into the tile (buffer instructions).  lane2_geometry checks that
+// every value and product fits.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int AXIS, int C, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
+{
+    __shared__ uint32_t ring[WPB * C * 64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint32_t* const rl = ring + wv * C * 64 + lane;
+    const int n = (int)((AXIS == 1) ? a.ny : a.nz);
+    const int64_t stride = (AXIS == 1) ? a.nx : a.nx * a.ny;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    const uint32_t hm = (1u << hb) - 1u;
+    const uint64_t ngroups = (a.ntiles + WPB - 1) / WPB;
+    const uint32_t us4 = (uint32_t)stride * 4u;
+    const uint32_t span = (uint32_t)(n - 1) * us4 + 256u;
+#define SLOT(k) (((k) & (C - 1)) * 64)
+
+    for (uint64_t t = blockIdx.x; t < ngroups; t += gridDim.x) {
+        const uint64_t tile = xcd_remap(t, ngroups) * WPB + wv;
+        if (tile >= a.ntiles)
+            continue;
+        const int64_t xb = (int64_t)(tile % (uint64_t)nxb), o = (int64_t)(tile / (uint64_t)nxb);
+        const int64_t x0 = xb * 64;
+        const bool valid = x0 + lane < a.nx;
+        const int64_t tb = ((AXIS == 1) ? o * a.nx * a.ny : o * a.nx) + x0;
+        const __amdgpu_buffer_rsrc_t rin = tile_rsrc(a.win + tb, span);
+        const __amdgpu_buffer_rsrc_t rout = tile_rsrc(a.w + tb, span);
+        const uint32_t vo = (valid ? (uint32_t)lane : 0u) * 4u;
+
+        int lo = 0, top = -1;
+        int c0 = 0, h0 = 0, dc = 0, dh = 0;     // top entry, difference to the one below
+        uint32_t t2p = 0;                        // packed entry two below the top
+        int fc0 = 0, fh0 = 0, dfc = 0, dfh = 0;  // front entry, difference to the next
+        uint32_t f2p = 0;                        // packed entry two after the front
+        int e = 0;                               // next row to emit
+        uint32_t be = 0xFFFFFFFFu;               // value at row e over the sites read so far
+        uint32_t eoff = vo, poff = vo, pval = QAI_WORD_INF;
+        bool ovf = false;
+
+        // the owner of row e: step while the next entry is strictly better
+        auto walk = [&]() {
+            if (lo < top && dfc < 2 * e * dfh) {
+#pragma unroll 1
+                do {
+                    ++lo;
+                    fc0 += dfc;
+                    fh0 += dfh;
+                    dfc = (int)(f2p >> hb) - fc0;
+                    dfh = (int)(f2p & hm) - fh0;
+                    f2p = rl[SLOT(lo + 2)];
+                } while (lo < top && dfc < 2 * e * dfh);
+            }
+            be = (uint32_t)(fc0 + e * (e - 2 * fh0));
+        };
+
+        auto row_step = [&](int i, uint32_t w) {
+            if (w != QAI_WORD_INF && !ovf) {
+                const int g = (int)(w >> 2);
+                const int cw = g + i * i;
+                if (top > lo) {
+                    bool rm = __mul24(dc, i - h0) - __mul24(cw - c0, dh) > 0;
+#pragma unroll 1
+                    while (rm) {
+                        --top;
+                        c0 -= dc;
+                        h0 -= dh;
+                        dc = c0 - (int)(t2p >> hb);
+                        dh = h0 - (int)(t2p & hm);
+                        t2p = rl[SLOT(top - 2)];
+                        rm = top > lo && __mul24(dc, i - h0) - __mul24(cw - c0, dh) > 0;
+                    }
+                }
+                if (top - lo + 1 >= C) {
+                    ovf = true;
+                } else {
+                    t2p = rl[SLOT(top - 1)];
+                    ++top;
+                    const uint32_t pk = ((uint32_t)cw << hb) | (uint32_t)i;
+                    rl[SLOT(top)] = pk;
+                    dc = cw - c0;
+                    dh = i - h0;
+                    c0 = cw;
+                    h0 = i;
+                    be = min(be, (uint32_t)(g + __mul24(e - i, e - i)));
+                    const int ws = top - lo;
+                    if (ws == 0) {
+                        fc0 = cw;
+                        fh0 = i;
+                    }
+                    if (ws == 1) {
+                        dfc = dc;
+                        dfh = dh;
+                    }
+                    if (ws == 2)
+                        f2p = pk;
+                }
+            }
+            // one emission slot per row (a lane with nothing final repeats its
+            // last store, so the memory operations per row stay fixed)
+            const int q = i + 1 - e;
+            const bool fin = !ovf && e <= i && top >= lo && be <= (uint32_t)__mul24(q, q);
+            const uint32_t off = fin ? eoff : poff;
+            const uint32_t val = fin ? (be << 2) : pval;
+            __builtin_amdgcn_raw_buffer_store_b32(val, rout, off, 0, 0);
+            poff = off;
+            pval = val;
+            if (fin) {
+                ++e;
+                eoff += us4;
+                walk();
+            }
+        };
+
+        // lanes whose live window nears the ring size emit all their final rows
+        auto catch_up = [&](int i) {
+#pragma unroll 1
+            for (int it = 0; it < n; ++it) {
+                const int q = i + 1 - e;
+                const bool fin = !ovf && top - lo + 1 > C - 9 && e <= i && be <= (uint32_t)__mul24(q, q);
+                if (__ballot(fin) == 0ull)
+                    break;
+                if (fin) {
+                    __builtin_amdgcn_raw_buffer_store_b32(be << 2, rout, eoff, 0, 0);
+                    ++e;
+                    eoff += us4;
+                    walk();
+                }
+            }
+        };
+
+        // full blocks of 16 rows (every prefetched word used before the
+        // catch-up loops), then the tail
+        const int nfull = n & ~15;
+        uint32_t A[8], B[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            A[k] = __builtin_amdgcn_raw_buffer_load_b32(rin, vo, (uint32_t)min(k, n - 1) * us4, 0);
+        for (int i0 = 0; i0 < nfull; i0 += 16) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                B[k] = __builtin_amdgcn_raw_buffer_load_b32(rin, vo, (uint32_t)(i0 + 8 + k) * us4, 0);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                row_step(i0 + k, A[k]);
+            catch_up(i0 + 7);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                A[k] = __builtin_amdgcn_raw_buffer_load_b32(rin, vo, (uint32_t)min(i0 + 16 + k, n - 1) * us4, 0);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                row_step(i0 + 8 + k, B[k]);
+            catch_up(i0 + 15);
+        }
+#pragma unroll 1
+        for (int i = nfull; i < n; ++i) {
+            row_step(i, __builtin_amdgcn_raw_buffer_load_b32(rin, vo, (uint32_t)i * us4, 0));
+            catch_up(i);
+        }
+        // every row left is final
+#pragma unroll 1
+        for (int it = 0; it < n; ++it) {
+            const bool more = !ovf && e < n;
+            if (__ballot(more) == 0ull)
+                break;
+            if (more) {
+                __builtin_amdgcn_raw_buffer_store_b32((top >= lo) ? (be << 2) : QAI_WORD_INF, rout, eoff, 0, 0);
+                ++e;
+                eoff += us4;
+                if (e < n && top >= lo)
+                    walk();
+            }
+        }
+#undef SLOT
+
+        // columns whose live window outgrew the ring: exact outward search,
+        // one column at a time by the whole wave
+        const uint32_t* __restrict__ inb = a.win + tb;
+        uint32_t* const outb = a.w + tb;
+        uint64_t om = __ballot(ovf && valid);
+        while (om) {
+            const int l = __ffsll((unsigned long long)om) - 1;
+            om &= om - 1ull;
+            for (int p = lane; p < n; p += 64) {
+                uint32_t best = inb[(int64_t)p * stride + l];
+                for (int r = 1; r < n; ++r) {
+                    const uint32_t r2 = (uint32_t)r * (uint32_t)r << 2;
+                    if (r2 > (best | 3u))
+                        break;
+                    const int l0 = p - r, h1 = p + r;
+                    if (l0 < 0 && h1 >= n)
+                        break;
+                    if (l0 >= 0) {
+                        const uint32_t cand = word_add(inb[(int64_t)l0 * stride + l], r2);
+                        if ((cand >> 2) <= (best >> 2))
+                            best = cand;
+                    }
+                    if (h1 < n) {
+                        const uint32_t cand = word_add(inb[(int64_t)h1 * stride + l], r2);
+                        if ((cand >> 2) < (best >> 2))
+                            best = cand;
+                    }
+                }
+                outb[(int64_t)p * stride + l] = best;
+            }
+        }
+    }
+}
+
 __global__ void k_clear(uint32_t* p, int n)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1984,6 +2202,34 @@ static bool lane_geometry(int axis, const EnvArgs& a, int& hb, bool& small)
     return n < 65536 && hb < 32 && gmax < ((int64_t)1 << (32 - hb));
 }
 
+// k_env_lane2 is exact when, with c_max = g_max + (n - 1)^2: packed entries
+// fit 32 bits (c_max < 2^(32 - hb)), every multiplied operand fits 24 bits
+// (c_max < 2^23), the two products of the removal test and their difference
+// stay in int32 (c_max n < 2^30), and the tile's byte span fits a buffer.
+static bool lane2_geometry(int axis, const EnvArgs& a, int& hb)
+{
+    const int64_t n = axis == 1 ? a.ny : a.nz;
+    const int64_t stride = axis == 1 ? a.nx : a.nx * a.ny;
+    const int64_t gmax = (a.nx - 1) * (a.nx - 1) + (axis == 2 ? (a.ny - 1) * (a.ny - 1) : 0);
+    const int64_t cmax = gmax + (n - 1) * (n - 1);
+    hb = 1;
+    while (((int64_t)1 << hb) < n)
+        ++hb;
+    return hb < 24 && cmax < ((int64_t)1 << (32 - hb)) && cmax < ((int64_t)1 << 23) &&
+           cmax * n < ((int64_t)1 << 30) && (n - 1) * stride * 4 + 256 < ((int64_t)1 << 31);
+}
+
+template <int AXIS>
+static hipError_t launch_lane2_t(EnvArgs a, int hb, hipStream_t s)
+{
+    constexpr int WPB = 4;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    a.ntiles = (uint64_t)(nxb * (AXIS == 1 ? a.nz : a.ny));
+    const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
+    hipLaunchKernelGGL((k_env_lane2<AXIS, 32, WPB>), dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a, hb);
+    return hipGetLastError();
+}
+
 template <int AXIS>
 static hipError_t launch_lane_t(EnvArgs a, int hb, bool small, hipStream_t s)
 {
@@ -2039,6 +2285,8 @@ hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_
     if (t.env_algo[axis] == 3 && !epi) {
         int hb;
         bool small;
+        if (lane2_geometry(axis, a, hb))
+            return axis == 1 ? launch_lane2_t<1>(a, hb, s) : launch_lane2_t<2>(a, hb, s);
         if (lane_geometry(axis, a, hb, small))
             return axis == 1 ? launch_lane_t<1>(a, hb, small, s) : launch_lane_t<2>(a, hb, small, s);
     }
