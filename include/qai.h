@@ -92,10 +92,12 @@ typedef struct {
 int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out, void* stream);
 
 /* Bytes of device workspace qai_mitigate_ex needs for dims: a 64 KiB header
- * (status word, reduction partials), three 32-bit words per voxel (the packed
- * distance words of the passes, ping-ponged) and one bit per voxel (flags of
- * the fused final pass: 128 bytes per 1024 voxels, rounded up), each part
- * rounded up to 256 bytes.  0 for invalid dims. */
+ * (status word, reduction partials), three buffers of 32-bit words (the packed
+ * distance words of the passes, ping-ponged), each of nz * ceil(ny/4)*4 * nx
+ * words (one per voxel, ny rounded up to a multiple of 4 for a blocked
+ * intermediate layout), and one bit per voxel (flags of the fused final pass:
+ * 128 bytes per 1024 voxels, rounded up), each part rounded up to 256 bytes.
+ * 0 for invalid dims. */
 size_t qai_workspace_bytes(const int64_t dims[3]);
 
 /* qai_mitigate_ex -- as qai_mitigate with explicit parameters (NULL = the

@@ -141,18 +141,21 @@ Tuning tuning_now() { return current_tuning(); }
 
 void prof_suppress(bool on) { g_prof_suppress += on ? 1 : -1; }
 
-uint32_t* word_buffer(void* ws, int64_t n, int k)
+// k-th region after the header; cap = word_capacity of the field
+uint32_t* word_buffer(void* ws, int64_t cap, int k)
 {
-    return (uint32_t*)((unsigned char*)ws + kHeaderBytes + (size_t)k * align256((size_t)n * 4));
+    return (uint32_t*)((unsigned char*)ws + kHeaderBytes + (size_t)k * align256((size_t)cap * 4));
 }
 
-void ws_buffers(void* ws, int64_t n, Plan1& p)
+// the field's extents must be set in p
+void ws_buffers(void* ws, Plan1& p)
 {
+    const int64_t cap = qai::word_capacity(p.nz, p.ny, p.nx);
     p.status = (uint32_t*)ws;
-    p.bufA = word_buffer(ws, n, 0);
-    p.bufB = word_buffer(ws, n, 1);
-    p.bufC = word_buffer(ws, n, 2);
-    p.flags = (uint64_t*)word_buffer(ws, n, 3);
+    p.bufA = word_buffer(ws, cap, 0);
+    p.bufB = word_buffer(ws, cap, 1);
+    p.bufC = word_buffer(ws, cap, 2);
+    p.flags = (uint64_t*)word_buffer(ws, cap, 3);
 }
 
 int tuning_to_abi(const Tuning& t, qai_tuning* out)
@@ -220,7 +223,7 @@ int plain_checked(const float* field, const int64_t dims[3], float eb, const qai
     pl.eb = eb;
     pl.eta = p.eta;
     pl.power = p.power;
-    ws_buffers(ws, n, pl);
+    ws_buffers(ws, pl);
     if (taps)
         pl.taps = *taps;
     const qai::Tuning t = current_tuning();
@@ -257,7 +260,8 @@ size_t qai_workspace_bytes(const int64_t dims[3])
             return 0;
     n = dims[0] * dims[1] * dims[2];
     // three word buffers, then the fused final pass's flag words
-    return kHeaderBytes + 3 * align256((size_t)n * 4) + align256(qai::flag_bytes(n));
+    const int64_t cap = qai::word_capacity(dims[0], dims[1], dims[2]);
+    return kHeaderBytes + 3 * align256((size_t)cap * 4) + align256(qai::flag_bytes(n));
 }
 
 int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const qai_params* params, void* ws,
@@ -326,8 +330,9 @@ int qai_backward(const float* grad_out, void* ws_saved, size_t ws_bytes, const i
         return fail(QAI_ENOWS, "workspace of %zu bytes needed, %zu given", need, ws_saved ? ws_bytes : (size_t)0);
     int k1, k2;
     qai::final_buffers(dims[0], dims[1], dims[2], k1, k2);
-    const uint32_t* w1 = word_buffer(ws_saved, n, k1);
-    const uint32_t* w2 = word_buffer(ws_saved, n, k2);
+    const int64_t cap = qai::word_capacity(dims[0], dims[1], dims[2]);
+    const uint32_t* w1 = word_buffer(ws_saved, cap, k1);
+    const uint32_t* w2 = word_buffer(ws_saved, cap, k2);
     hipError_t e = qai::launch_backward(grad_out, w1, w2, n, eb, p.eta, p.power,
                                         (double*)((unsigned char*)ws_saved + kPartialOffset), grad_params,
                                         (hipStream_t)stream);

@@ -249,7 +249,7 @@ int qai_batch_plan_create(int n, const float* const* fields, const int64_t (*dim
         pl.eb = ebs[i];
         pl.eta = prm.eta;
         pl.power = prm.power;
-        ws_buffers(cur, voxels(dims[i]), pl);
+        ws_buffers(cur, pl);
         cur += align256(qai_workspace_bytes(dims[i]));
         p->order.push_back(i);
     }

@@ -101,6 +101,11 @@ hipError_t run_plain(Plan1& p, const Tuning& t, hipStream_t s);
 // per 64 voxels, in blocks of 1024 voxels.
 inline size_t flag_bytes(int64_t n) { return (size_t)((n + 1023) / 1024) * 128; }
 
+// Words per distance-word buffer: the voxel count with ny rounded up to a
+// multiple of 4, room for the blocked layout [z][y/4][x][y%4] in which the
+// second EDT's y pass hands its result to the needed-voxel search.
+inline int64_t word_capacity(int64_t nz, int64_t ny, int64_t nx) { return nz * ((ny + 3) / 4) * 4 * nx; }
+
 // Stage-timing hooks (active when profiling is enabled).
 void prof_begin(const char* name, hipStream_t s);
 void prof_end(hipStream_t s);
@@ -116,8 +121,8 @@ int check_eb(float eb);
 int check_params(const qai_params* p, qai_params* out);
 Tuning tuning_now();
 void prof_suppress(bool on);               // pause stage timing on this thread (nests)
-uint32_t* word_buffer(void* ws, int64_t n, int k);
-void ws_buffers(void* ws, int64_t n, Plan1& p); // status word and the three word buffers
+uint32_t* word_buffer(void* ws, int64_t cap, int k); // k-th region, cap = word_capacity
+void ws_buffers(void* ws, Plan1& p); // status word, the three word buffers and the flags (extents set in p)
 int tuning_to_abi(const Tuning& t, qai_tuning* out);
 } // namespace api
 

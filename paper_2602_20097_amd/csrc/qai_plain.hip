@@ -648,7 +648,25 @@ struct ZsArgs {
     uint64_t* flags;      // four ballot words per wave of k_interp_own
     int64_t nx, ny, nz;
     float eta_eb, power;
+    bool blk;             // gy in the blocked layout [z][y/4][x][y%4] (else natural)
 };
+
+// index of voxel i's word in gy, and the distance between consecutive z-planes there
+template <bool BLK>
+__device__ __forceinline__ int64_t gy_index(const ZsArgs& a, int64_t i)
+{
+    if (!BLK)
+        return i;
+    const int64_t plane = a.nx * a.ny;
+    const int64_t z = i / plane, r = i - z * plane;
+    const int64_t y = r / a.nx, x = r - y * a.nx;
+    return ((z * ((a.ny + 3) >> 2) + (y >> 2)) * a.nx + x) * 4 + (y & 3);
+}
+template <bool BLK>
+__device__ __forceinline__ int64_t gy_plane(const ZsArgs& a)
+{
+    return BLK ? ((a.ny + 3) >> 2) * 4 * a.nx : a.nx * a.ny;
+}
 
 // Loads of the y-pass words by 32-bit byte offset (buffer loads, fields below
 // 2^30 voxels) or by 64-bit index.
@@ -741,11 +759,11 @@ __device__ __forceinline__ bool interp_near(const ZsArgs& a, int64_t i, uint32_t
     return true;
 }
 
-template <bool BUF>
+template <bool BUF, bool BLK>
 __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
 {
     const int64_t n = a.nx * a.ny * a.nz;
-    const GyReader<BUF> g(a.gy, n);
+    const GyReader<BUF> g(a.gy, gy_plane<BLK>(a) * a.nz);
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     bool far[4] = {false, false, false, false};
     uint32_t w[4];
@@ -765,7 +783,7 @@ __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
     uint32_t gv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        gv[k] = (word_sign(w[k]) != 0 && word_d2(w[k]) != 0u) ? g.at(i0 + k) : QAI_WORD_INF;
+        gv[k] = (word_sign(w[k]) != 0 && word_d2(w[k]) != 0u) ? g.at(gy_index<BLK>(a, i0 + k)) : QAI_WORD_INF;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         far[k] = !interp_near(a, i0 + k, w[k], x[k], gv[k], o[k]);
@@ -792,14 +810,14 @@ __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
 // block's flagged voxels are listed in LDS (block-wide prefix sum of the word
 // popcounts) and dealt one per thread; lists longer than the LDS window go in
 // several rounds.
-template <bool BUF>
+template <bool BUF, bool BLK>
 __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords)
 {
     constexpr int L = 1024;
     __shared__ int64_t list[L];
     __shared__ int wsum[4];
-    const int64_t plane = a.nx * a.ny;
-    const GyReader<BUF> g(a.gy, plane * a.nz);
+    const int64_t plane = a.nx * a.ny, gplane = gy_plane<BLK>(a);
+    const GyReader<BUF> g(a.gy, gplane * a.nz);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t grp = (int64_t)blockIdx.x + (int64_t)(tid >> 2) * gridDim.x; // wave of k_interp_own
     const int64_t wi = grp * 4 + (tid & 3);
@@ -845,11 +863,23 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords)
             const int64_t i = list[j];
             const uint32_t w = a.w1[i];
             const float xv = a.xq[i];
-            const uint32_t d2 = zsearch<BUF>(g, i, plane, (int)(i / plane), (int)a.nz);
+            const uint32_t d2 = zsearch<BUF>(g, gy_index<BLK>(a, i), gplane, (int)(i / plane), (int)a.nz);
             a.out[i] = interp_at(a, i, w, xv, d2);
         }
         __syncthreads();
     }
+}
+
+template <bool BUF, bool BLK>
+static hipError_t launch_interp_search_t(const ZsArgs& a, int64_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_interp_own<BUF, BLK>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int64_t nwords = blocks * 16; // flag_bytes(n) / 8
+    hipLaunchKernelGGL((k_interp_far<BUF, BLK>), dim3((unsigned)((nwords / 4 + 63) / 64)), dim3(256), 0, s, a, nwords);
+    return hipGetLastError();
 }
 
 static hipError_t launch_interp_search(const ZsArgs& a, hipStream_t s)
@@ -860,21 +890,11 @@ static hipError_t launch_interp_search(const ZsArgs& a, hipStream_t s)
     const int64_t blocks = (n + 1023) / 1024;
     if (blocks > 0x7FFFFFFF)
         return hipErrorInvalidValue;
-    const bool buf = n < ((int64_t)1 << 29);
+    // buffer loads by 32-bit byte offset while gy (natural or blocked) stays below 2^31 bytes
+    const bool buf = word_capacity(a.nz, a.ny, a.nx) < ((int64_t)1 << 29);
     if (buf)
-        hipLaunchKernelGGL(k_interp_own<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_interp_own<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    const int64_t nwords = blocks * 16; // flag_bytes(n) / 8
-    const dim3 grid((unsigned)((nwords / 4 + 63) / 64));
-    if (buf)
-        hipLaunchKernelGGL(k_interp_far<true>, grid, dim3(256), 0, s, a, nwords);
-    else
-        hipLaunchKernelGGL(k_interp_far<false>, grid, dim3(256), 0, s, a, nwords);
-    return hipGetLastError();
+        return a.blk ? launch_interp_search_t<true, true>(a, blocks, s) : launch_interp_search_t<true, false>(a, blocks, s);
+    return a.blk ? launch_interp_search_t<false, true>(a, blocks, s) : launch_interp_search_t<false, false>(a, blocks, s);
 }
 
 // --------------------------------------------------------- envelope pass
@@ -1758,10 +1778,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void* p, uint3
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-template <int AXIS, int C, int WPB>
+// BLK (y pass only): the result goes out in the blocked layout
+// [z][y/4][x][y%4]: a lane collects its final rows in LDS and writes each
+// group of four as one 16-byte store, a quarter of the write requests of
+// single-word stores scattered over 64 rows.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int AXIS, int C, int WPB, bool BLK>
 __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
 {
+    static_assert(!BLK || AXIS == 1, "blocked output is for the y pass");
     __shared__ uint32_t ring[WPB * C * 64];
+    __shared__ __align__(16) uint32_t stage[BLK ? WPB * 64 * 4 : 4];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     uint32_t* const rl = ring + wv * C * 64 + lane;
@@ -1772,6 +1800,8 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
     const uint64_t ngroups = (a.ntiles + WPB - 1) / WPB;
     const uint32_t us4 = (uint32_t)stride * 4u;
     const uint32_t span = (uint32_t)(n - 1) * us4 + 256u;
+    const int64_t ny4 = (a.ny + 3) >> 2;
+    uint32_t* const sl = stage + (BLK ? (wv * 64 + lane) * 4 : 0);
 #define SLOT(k) (((k) & (C - 1)) * 64)
 
     for (uint64_t t = blockIdx.x; t < ngroups; t += gridDim.x) {
@@ -1782,9 +1812,25 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
         const int64_t x0 = xb * 64;
         const bool valid = x0 + lane < a.nx;
         const int64_t tb = ((AXIS == 1) ? o * a.nx * a.ny : o * a.nx) + x0;
+        // blocked: the tile's words start at (o ny4 nx + x0) 4; row group k
+        // of lane l lies (k nx + l) 16 bytes further
+        const int64_t tbo = BLK ? (o * ny4 * a.nx + x0) * 4 : tb;
+        const uint32_t span_out = BLK ? (uint32_t)(((ny4 - 1) * a.nx + 64) * 16) : span;
         const __amdgpu_buffer_rsrc_t rin = tile_rsrc(a.win + tb, span);
-        const __amdgpu_buffer_rsrc_t rout = tile_rsrc(a.w + tb, span);
+        const __amdgpu_buffer_rsrc_t rout = tile_rsrc(a.w + tbo, span_out);
         const uint32_t vo = (valid ? (uint32_t)lane : 0u) * 4u;
+        const uint32_t bo = (valid ? (uint32_t)lane : 0u) * 16u;
+        const uint32_t bstep = (uint32_t)a.nx * 16u;
+
+        // blocked: the final value v of a row goes to the lane's stage, and out
+        // with the fourth row of its group or the last row of the line
+        auto emit_blk = [&](int row, uint32_t v) {
+            sl[row & 3] = v;
+            if ((row & 3) == 3 || row == n - 1) {
+                const u32x4 q = *reinterpret_cast<const u32x4*>(sl);
+                __builtin_amdgcn_raw_buffer_store_b128(q, rout, bo + (uint32_t)(row >> 2) * bstep, 0, 0);
+            }
+        };
 
         int lo = 0, top = -1;
         int c0 = 0, h0 = 0, dc = 0, dh = 0;     // top entry, difference to the one below
@@ -1854,15 +1900,20 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
                         f2p = pk;
                 }
             }
-            // one emission slot per row (a lane with nothing final repeats its
-            // last store, so the memory operations per row stay fixed)
+            // one emission slot per row (unblocked: a lane with nothing final
+            // repeats its last store, so the memory operations per row stay fixed)
             const int q = i + 1 - e;
             const bool fin = !ovf && e <= i && top >= lo && be <= (uint32_t)__mul24(q, q);
-            const uint32_t off = fin ? eoff : poff;
-            const uint32_t val = fin ? (be << 2) : pval;
-            __builtin_amdgcn_raw_buffer_store_b32(val, rout, off, 0, 0);
-            poff = off;
-            pval = val;
+            if (BLK) {
+                if (fin)
+                    emit_blk(e, be << 2);
+            } else {
+                const uint32_t off = fin ? eoff : poff;
+                const uint32_t val = fin ? (be << 2) : pval;
+                __builtin_amdgcn_raw_buffer_store_b32(val, rout, off, 0, 0);
+                poff = off;
+                pval = val;
+            }
             if (fin) {
                 ++e;
                 eoff += us4;
@@ -1879,7 +1930,10 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
                 if (__ballot(fin) == 0ull)
                     break;
                 if (fin) {
-                    __builtin_amdgcn_raw_buffer_store_b32(be << 2, rout, eoff, 0, 0);
+                    if (BLK)
+                        emit_blk(e, be << 2);
+                    else
+                        __builtin_amdgcn_raw_buffer_store_b32(be << 2, rout, eoff, 0, 0);
                     ++e;
                     eoff += us4;
                     walk();
@@ -1922,7 +1976,11 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
             if (__ballot(more) == 0ull)
                 break;
             if (more) {
-                __builtin_amdgcn_raw_buffer_store_b32((top >= lo) ? (be << 2) : QAI_WORD_INF, rout, eoff, 0, 0);
+                const uint32_t v = (top >= lo) ? (be << 2) : QAI_WORD_INF;
+                if (BLK)
+                    emit_blk(e, v);
+                else
+                    __builtin_amdgcn_raw_buffer_store_b32(v, rout, eoff, 0, 0);
                 ++e;
                 eoff += us4;
                 if (e < n && top >= lo)
@@ -1934,7 +1992,7 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
         // columns whose live window outgrew the ring: exact outward search,
         // one column at a time by the whole wave
         const uint32_t* __restrict__ inb = a.win + tb;
-        uint32_t* const outb = a.w + tb;
+        uint32_t* const outb = a.w + tbo;
         uint64_t om = __ballot(ovf && valid);
         while (om) {
             const int l = __ffsll((unsigned long long)om) - 1;
@@ -1959,7 +2017,10 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
                             best = cand;
                     }
                 }
-                outb[(int64_t)p * stride + l] = best;
+                if (BLK)
+                    outb[((int64_t)(p >> 2) * a.nx + l) * 4 + (p & 3)] = best;
+                else
+                    outb[(int64_t)p * stride + l] = best;
             }
         }
     }
@@ -2219,14 +2280,15 @@ static bool lane2_geometry(int axis, const EnvArgs& a, int& hb)
            cmax * n < ((int64_t)1 << 30) && (n - 1) * stride * 4 + 256 < ((int64_t)1 << 31);
 }
 
-template <int AXIS>
+template <int AXIS, bool BLK = false>
 static hipError_t launch_lane2_t(EnvArgs a, int hb, hipStream_t s)
 {
     constexpr int WPB = 4;
     const int64_t nxb = (a.nx + 63) >> 6;
     a.ntiles = (uint64_t)(nxb * (AXIS == 1 ? a.nz : a.ny));
     const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
-    hipLaunchKernelGGL((k_env_lane2<AXIS, 32, WPB>), dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a, hb);
+    hipLaunchKernelGGL((k_env_lane2<AXIS, 32, WPB, BLK>), dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a,
+                       hb);
     return hipGetLastError();
 }
 
@@ -2427,23 +2489,33 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
     QAI_TRY(launch_seed(1, sa, s, t.seed_ty, t.seed_tz));
     prof_end(s);
 
-    // remaining passes of step D
+    // remaining passes of step D; without taps, a 3-D field's last pass runs
+    // only where step E needs it (the needed-voxel search), and the y pass
+    // hands it its result in the blocked layout when the per-lane envelope
+    // runs it
+    const qai_taps& tp = p.taps;
+    const bool any_tap = tp.q || tp.b1 || tp.sb || tp.s || tp.d1sq || tp.b2 || tp.d2sq || tp.w;
+    const bool aligned = (((uintptr_t)buf[w1] | (uintptr_t)p.xq | (uintptr_t)p.out) & 15u) == 0;
+    const bool search = p.nz > 1 && !any_tap && t_in.env_algo[2] < 0 && p.flags && aligned;
+    bool blk = false;
     if (p.ny > 1) {
         const int nx2 = (c2 == o0) ? o1 : o0;
         ea.win = buf[c2];
         ea.w = buf[nx2];
+        int hb = 0;
+        blk = search && t.env_algo[1] == 3 && lane2_geometry(1, ea, hb);
         prof_begin("edt2_y", s);
-        QAI_TRY(launch_env(1, false, ea, t, s));
+        if (blk)
+            QAI_TRY((launch_lane2_t<1, true>(ea, hb, s)));
+        else
+            QAI_TRY(launch_env(1, false, ea, t, s));
         prof_end(s);
         c2 = nx2;
     }
-    const qai_taps& tp = p.taps;
-    const bool any_tap = tp.q || tp.b1 || tp.sb || tp.s || tp.d1sq || tp.b2 || tp.d2sq || tp.w;
-    const bool aligned = (((uintptr_t)buf[w1] | (uintptr_t)p.xq | (uintptr_t)p.out) & 15u) == 0;
-    if (p.nz > 1 && !any_tap && t_in.env_algo[2] < 0 && p.flags && aligned) {
+    if (search) {
         // last pass of step D only at needed voxels, fused with step E
         const int nx2 = (c2 == o0) ? o1 : o0;
-        ZsArgs za = {buf[w1], buf[c2], buf[nx2], p.xq, p.out, p.flags, p.nx, p.ny, p.nz, p.eta * p.eb, p.power};
+        ZsArgs za = {buf[w1], buf[c2], buf[nx2], p.xq, p.out, p.flags, p.nx, p.ny, p.nz, p.eta * p.eb, p.power, blk};
         prof_begin("edt2_z_interp", s);
         QAI_TRY(launch_interp_search(za, s));
         prof_end(s);

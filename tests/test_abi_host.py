@@ -34,10 +34,11 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_workspace_bytes(lib):
-    for shape in ((1, 1, 1), (64, 64, 64), (256, 384, 384), (1, 1800, 3600)):
+    for shape in ((1, 1, 1), (64, 64, 64), (256, 384, 384), (1, 1800, 3600), (3, 5, 7)):
         n = math.prod(shape)
         b = lib.qai_workspace_bytes(_lib.Dims(*shape))
-        words = 3 * (((n * 4) + 255) // 256) * 256
+        cap = shape[0] * ((shape[1] + 3) // 4) * 4 * shape[2]
+        words = 3 * (((cap * 4) + 255) // 256) * 256
         bits = (((n + 1023) // 1024 * 128 + 255) // 256) * 256
         assert b == 64 * 1024 + words + bits
     for bad in ((0, 4, 4), (4, -1, 4), (1, 1, 16385)):

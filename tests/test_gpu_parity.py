@@ -162,6 +162,24 @@ def test_headline_512_full_parity():
     assert np.abs(g["out"].astype(np.float64) - x32).max() <= (1 + 0.9) * eb * (1 + 1e-6)
 
 
+def test_blocked_handoff_to_the_needed_voxel_search():
+    """With the second EDT's y pass on the per-lane envelope and its z pass
+    automatic, a call without taps hands the y result to the needed-voxel
+    search in the blocked layout [z][y/4][x][y%4] (rows per plane that are not
+    a multiple of 4 exercise its padding); the output matches the tapped call
+    bit for bit and the oracle."""
+    import paper_2602_20097_amd as qai
+    base = qai.get_tuning()
+    try:
+        qai.set_tuning(edt2_algo=[3, -1])
+        for shape in ((6, 70, 130), (9, 33, 65), (5, 31, 100), (3, 64, 64), (2, 2, 300)):
+            x32, xq, q, eb = synth.quantize(synth.grf(shape, 2.5, 77 + sum(shape)), 2e-2)
+            assert_parity(xq, eb, label=f"blocked {shape}")
+    finally:
+        qai.set_tuning(None)
+    assert qai.get_tuning() == base
+
+
 def test_every_pass_algorithm_gives_the_same_transform():
     """Each per-pass algorithm choice (qai_tuning) computes the same exact EDTs."""
     import paper_2602_20097_amd as qai
