@@ -25,13 +25,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # kernel symbol -> bench stage (the plain path launches one kernel per stage)
 STAGES = [
-    (r"k_seed_(reg|slab|xscan)<0", "seed1_xscan"),
-    (r"k_seed_(reg|slab|xscan)<1", "seed2_xscan"),
-    (r"k_env_lane_epi", "edt2_z_interp"),
-    (r"k_interp", "interp"),
+    (r"k_seed_(reg|slab|xscan|lines)<0", "seed1_xscan"),
+    (r"k_seed_(reg|slab|xscan|lines)<1", "seed2_xscan"),
+    (r"k_interp_(own|far)", "edt2_z_interp"),
+    (r"k_interp\b", "interp"),
     (r"k_copy", "copy_probe"),
     (r"k_clear", "clear"),
 ]
+SEED1 = r"k_seed_(reg|slab|xscan|lines)<0"
+SEED2 = r"k_seed_(reg|slab|xscan|lines)<1"
 
 
 def kernel_rev():
@@ -72,24 +74,40 @@ def read_stats(d):
     return rows
 
 
-def read_trace_stages(d):
-    """Per-stage average duration from the kernel trace (dispatch order decides
-    which envelope kernel belongs to which EDT)."""
-    path = _one(os.path.join(d, "**", "*kernel_trace.csv"))
-    per = {}
-    seen_seed2 = False
-    with open(path) as fh:
-        rows = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
-    for r in rows:
-        name = r["Kernel_Name"]
-        if re.search(r"k_seed_(reg|slab|xscan)<0", name):
+def _per_step(events):
+    """events: (name, value) in dispatch order.  A step starts at its first
+    seed kernel; the values of a stage's kernels are summed within a step and
+    averaged over steps (the copy probe, outside the steps, per launch)."""
+    steps, cur, seen_seed2 = [], None, False
+    copy = []
+    for name, val in events:
+        if re.search(SEED1, name):
+            cur = {}
+            steps.append(cur)
             seen_seed2 = False
-        if re.search(r"k_seed_(reg|slab|xscan)<1", name):
+        if re.search(SEED2, name):
             seen_seed2 = True
         st = stage_of(name, 1 if seen_seed2 else 0)
-        if st:
-            per.setdefault(st, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    return {k: (statistics.mean(v), len(v)) for k, v in per.items()}
+        if st == "copy_probe":
+            copy.append(val)
+        elif st and cur is not None:
+            cur[st] = cur.get(st, 0.0) + val
+    out = {}
+    for st in sorted({k for s in steps for k in s}):
+        vals = [s[st] for s in steps if st in s]
+        out[st] = (statistics.mean(vals), len(vals))
+    if copy:
+        out["copy_probe"] = (statistics.mean(copy), len(copy))
+    return out
+
+
+def read_trace_stages(d):
+    """Per-stage duration per step from the kernel trace (dispatch order decides
+    which envelope kernel belongs to which EDT)."""
+    path = _one(os.path.join(d, "**", "*kernel_trace.csv"))
+    with open(path) as fh:
+        rows = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
+    return _per_step([(r["Kernel_Name"], int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in rows])
 
 
 def read_counter(d, counter):
@@ -102,18 +120,8 @@ def read_counter(d, counter):
             key = int(r["Dispatch_Id"])
             name, val = r["Kernel_Name"], float(r["Counter_Value"])
             disp.setdefault(key, [name, 0.0])[1] += val
-    per = {}
-    seen_seed2 = False
-    for key in sorted(disp):
-        name, kib = disp[key]
-        if re.search(r"k_seed_(reg|slab|xscan)<0", name):
-            seen_seed2 = False
-        if re.search(r"k_seed_(reg|slab|xscan)<1", name):
-            seen_seed2 = True
-        st = stage_of(name, 1 if seen_seed2 else 0)
-        if st:
-            per.setdefault(st, []).append(kib)
-    return {k: statistics.mean(v) for k, v in per.items()}
+    per = _per_step([tuple(disp[k]) for k in sorted(disp)])
+    return {k: v[0] for k, v in per.items()}
 
 
 def main():
@@ -139,7 +147,8 @@ def main():
         nm = r["name"].replace("|", "/")
         lines.append(f"| `{nm[:90]}` | {r['calls']} | {r['avg_ns'] / 1e3:.1f} | {r['total_ns'] / 1e6:.2f} | "
                      f"{r['pct']:.1f} |")
-    lines += ["", "## Per stage (kernel trace, dispatch order)", "", "| stage | launches | avg us |", "|---|---|---|"]
+    lines += ["", "## Per stage and step (kernel trace, dispatch order; a stage's kernels summed)", "",
+              "| stage | steps | avg us |", "|---|---|---|"]
     for st, (avg, cnt) in stages.items():
         lines.append(f"| {st} | {cnt} | {avg / 1e3:.1f} |")
 
@@ -152,7 +161,7 @@ def main():
         lines += ["", "## HBM traffic per launch (FETCH_SIZE, WRITE_SIZE)", "",
                   f"Scale factors from the copy probe ({args.copy_words} words each way): "
                   f"fetch x{kf:.3f}, write x{kw:.3f}.", "",
-                  "| stage | fetch MiB (raw) | write MiB (raw) | bytes/launch (scaled) | bytes/voxel |",
+                  "| stage | fetch MiB (raw) | write MiB (raw) | bytes/step (scaled) | bytes/voxel |",
                   "|---|---|---|---|---|"]
         tfile = os.path.join(ROOT, "profiles", "traffic.json")
         tr = {}
