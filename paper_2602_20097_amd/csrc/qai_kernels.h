@@ -37,14 +37,6 @@ struct EnvArgs {
     int64_t nx, ny, nz;
     int tx_log2;          // columns per tile = 1 << tx_log2
     uint64_t ntiles;
-    bool write_words;     // store the pass result (always, except an epilogue pass that need not)
-    // epilogue
-    const uint32_t* w1;
-    const float* xq;
-    float* out;
-    float eta_eb, power;
-    int32_t* td2;
-    float* tw;
 };
 
 struct InterpArgs {
@@ -73,7 +65,7 @@ void default_tuning(Tuning& t);
 
 // Host launchers: return hipSuccess or the launch error.
 hipError_t launch_seed(int mode, const SeedArgs& a, hipStream_t s, int ty, int tz);
-hipError_t launch_env(int axis, bool epilogue, EnvArgs a, const Tuning& t, hipStream_t s);
+hipError_t launch_env(int axis, EnvArgs a, const Tuning& t, hipStream_t s);
 hipError_t launch_interp(const InterpArgs& a, hipStream_t s);
 hipError_t launch_clear(uint32_t* p, int n, hipStream_t s);
 

@@ -1,18 +1,22 @@
 // qai_plain.hip -- kernels of the plain QAI post-pass for gfx950.
 //
 // Stage map (Algorithm 4 of the paper):
-//   k_seed_xscan<0>  step A (Algorithm 2) fused with the x pass of step B:
+//   k_seed_*<0>      step A (Algorithm 2) fused with the x pass of step B:
 //                    x' -> q -> B1 and S_B by a 6-neighbour stencil, then
 //                    each voxel's nearest B1 voxel on its x-line.
-//   k_env<y|z>       remaining passes of step B: exact 1-D lower-envelope
-//                    minimisation of g(j) + (i - j)^2 along y, then z
-//                    (Algorithm 1's result, sign payload carried along).
-//   k_seed_xscan<1>  step C (Algorithm 3): propagated S read from the final
+//   k_env_*          remaining passes of step B: exact 1-D minimisation of
+//                    g(j) + (i - j)^2 along y, then z (Algorithm 1's result,
+//                    sign payload carried along).
+//   k_seed_*<1>      step C (Algorithm 3): propagated S read from the final
 //                    words, B2 by a 6-neighbour stencil, then the x pass of
 //                    step D.
-//   k_env<y|z>       remaining passes of step D; the last one ends with
-//                    step E (interpolation and compensation) in registers.
-// All kernels are memory bound: no dense contraction exists on this path.
+//   k_env_*          the y pass of step D, then either the z pass and
+//                    k_interp (step E), or, for a 3-D call without taps,
+//                    k_interp_own / k_interp_far: step E with the z pass
+//                    done only where the weight depends on it.
+// No dense contraction exists on this path: the stencil and scan kernels are
+// bound by VALU issue, the envelope and search kernels by dependent latency,
+// the streaming ones by HBM.
 #include "qai_device.h"
 #include "qai_kernels.h"
 #include <type_traits>
@@ -905,7 +909,7 @@ static hipError_t launch_interp_search(const ZsArgs& a, hipStream_t s)
 // least d^2.  At equal value the lower coordinate wins (left candidates win
 // ties, right ones need to be strictly better), the choice Algorithm 1's
 // strict comparisons make.
-template <int AXIS, bool EPI>
+template <int AXIS>
 __global__ __launch_bounds__(256) void k_env_window(EnvArgs a)
 {
     extern __shared__ __align__(16) uint32_t tile[];
@@ -955,11 +959,7 @@ __global__ __launch_bounds__(256) void k_env_window(EnvArgs a)
                         best = cand;
                 }
             }
-            const int64_t gi = base + (int64_t)r * stride + c;
-            if (a.write_words)
-                a.w[gi] = best;
-            if (EPI)
-                interp_store(gi, best, a.w1, a.xq, a.out, a.eta_eb, a.power, a.td2, a.tw);
+            a.w[base + (int64_t)r * stride + c] = best;
         }
     }
 }
@@ -1143,7 +1143,7 @@ struct Band2 {
     }
 };
 
-template <int AXIS, bool EPI, int M>
+template <int AXIS, int M>
 __global__ __launch_bounds__(1024) void k_env_band2(EnvArgs a, int lb)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1326,17 +1326,12 @@ __global__ __launch_bounds__(1024) void k_env_band2(EnvArgs a, int lb)
             L.G[cbase + j] = res[j];
         __syncthreads();
 
-        // coalesced store (and step E when this is the last pass)
+        // coalesced store
         for (int i = tid; i < total; i += blockDim.x) {
             const int r = i >> txl, cc = i & (Tx - 1);
             if (x0 + cc >= a.nx)
                 continue;
-            const uint32_t word = L.G[L.at(cc, r)];
-            const int64_t gi = base + (int64_t)r * stride + cc;
-            if (a.write_words)
-                a.w[gi] = word;
-            if (EPI)
-                interp_store(gi, word, a.w1, a.xq, a.out, a.eta_eb, a.power, a.td2, a.tw);
+            a.w[base + (int64_t)r * stride + cc] = L.G[L.at(cc, r)];
         }
     }
 }
@@ -2163,28 +2158,28 @@ static int default_tx_log2(int64_t n)
     return l;
 }
 
-template <int AXIS, bool EPI, int M>
+template <int AXIS, int M>
 static hipError_t launch_band2_t(EnvArgs a, int lb, size_t lds, int threads, uint32_t grid, hipStream_t s)
 {
     static bool attr_done = false;
     if (lds > 64 * 1024 && !attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_env_band2<AXIS, EPI, M>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_env_band2<AXIS, M>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess)
             return e;
         attr_done = true;
     }
-    hipLaunchKernelGGL((k_env_band2<AXIS, EPI, M>), dim3(grid), dim3(threads), lds, s, a, lb);
+    hipLaunchKernelGGL((k_env_band2<AXIS, M>), dim3(grid), dim3(threads), lds, s, a, lb);
     return hipGetLastError();
 }
 
-template <int AXIS, bool EPI>
+template <int AXIS>
 static hipError_t launch_band2_m(EnvArgs a, int M, int lb, size_t lds, int threads, uint32_t grid, hipStream_t s)
 {
     switch (M) {
-    case 8: return launch_band2_t<AXIS, EPI, 8>(a, lb, lds, threads, grid, s);
-    case 16: return launch_band2_t<AXIS, EPI, 16>(a, lb, lds, threads, grid, s);
-    default: return launch_band2_t<AXIS, EPI, 32>(a, lb, lds, threads, grid, s);
+    case 8: return launch_band2_t<AXIS, 8>(a, lb, lds, threads, grid, s);
+    case 16: return launch_band2_t<AXIS, 16>(a, lb, lds, threads, grid, s);
+    default: return launch_band2_t<AXIS, 32>(a, lb, lds, threads, grid, s);
     }
 }
 
@@ -2211,7 +2206,7 @@ static void band2_geometry(int n, int want_txl, int& M, int& lb, int& txl, size_
     lds = (size_t)(B * (M + 1) + 1) * (1 << txl) * 8;
 }
 
-static hipError_t launch_band2(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_t s)
+static hipError_t launch_band2(int axis, EnvArgs a, const Tuning& t, hipStream_t s)
 {
     const int n = (int)(axis == 1 ? a.ny : a.nz);
     int M, lb, txl;
@@ -2223,10 +2218,8 @@ static hipError_t launch_band2(int axis, bool epi, EnvArgs a, const Tuning& t, h
     const uint32_t grid = grid_cap(a.ntiles, 1u << 20);
     const int threads = (1 << lb) << txl;
     if (axis == 1)
-        return epi ? launch_band2_m<1, true>(a, M, lb, lds, threads, grid, s)
-                   : launch_band2_m<1, false>(a, M, lb, lds, threads, grid, s);
-    return epi ? launch_band2_m<2, true>(a, M, lb, lds, threads, grid, s)
-               : launch_band2_m<2, false>(a, M, lb, lds, threads, grid, s);
+        return launch_band2_m<1>(a, M, lb, lds, threads, grid, s);
+    return launch_band2_m<2>(a, M, lb, lds, threads, grid, s);
 }
 
 template <int AXIS, int C>
@@ -2318,7 +2311,7 @@ static hipError_t launch_swin_t(EnvArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_t s)
+hipError_t launch_env(int axis, EnvArgs a, const Tuning& t, hipStream_t s)
 {
     const int64_t n = axis == 1 ? a.ny : a.nz;
     if (t.env_algo[axis] == 1) {
@@ -2331,20 +2324,17 @@ hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_
         const uint32_t grid = grid_cap(a.ntiles, 1u << 20);
         const size_t shm = (size_t)(n << txl) * 4;
         const dim3 blk(t.env_threads > 0 ? t.env_threads : 256);
-        if (axis == 1) {
-            if (epi) hipLaunchKernelGGL((k_env_window<1, true>), dim3(grid), blk, shm, s, a);
-            else hipLaunchKernelGGL((k_env_window<1, false>), dim3(grid), blk, shm, s, a);
-        } else {
-            if (epi) hipLaunchKernelGGL((k_env_window<2, true>), dim3(grid), blk, shm, s, a);
-            else hipLaunchKernelGGL((k_env_window<2, false>), dim3(grid), blk, shm, s, a);
-        }
+        if (axis == 1)
+            hipLaunchKernelGGL((k_env_window<1>), dim3(grid), blk, shm, s, a);
+        else
+            hipLaunchKernelGGL((k_env_window<2>), dim3(grid), blk, shm, s, a);
         return hipGetLastError();
     }
     if (t.env_algo[axis] == 2 && n <= 64 * 32)
-        return launch_band2(axis, epi, a, t, s);
-    if (t.env_algo[axis] == 4 && !epi)
+        return launch_band2(axis, a, t, s);
+    if (t.env_algo[axis] == 4)
         return axis == 1 ? launch_swin_t<1>(a, s) : launch_swin_t<2>(a, s);
-    if (t.env_algo[axis] == 3 && !epi) {
+    if (t.env_algo[axis] == 3) {
         int hb;
         bool small;
         if (lane2_geometry(axis, a, hb))
@@ -2352,8 +2342,6 @@ hipError_t launch_env(int axis, bool epi, EnvArgs a, const Tuning& t, hipStream_
         if (lane_geometry(axis, a, hb, small))
             return axis == 1 ? launch_lane_t<1>(a, hb, small, s) : launch_lane_t<2>(a, hb, small, s);
     }
-    if (epi)
-        return hipErrorInvalidValue; // the streaming pass never carries step E
     const int cap = t.stream_cap[axis] <= 16 ? 16 : (t.stream_cap[axis] <= 32 ? 32 : 64);
     if (axis == 1)
         return cap == 16 ? launch_stream_t<1, 16>(a, s)
@@ -2456,7 +2444,6 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
     ea.nx = p.nx;
     ea.ny = p.ny;
     ea.nz = p.nz;
-    ea.write_words = true;
     Tuning t1 = t; // the first EDT: dense boundaries, short owner distances
     for (int i = 0; i < 3; ++i) {
         t1.stream_cap[i] = t.edt1_cap[i];
@@ -2466,7 +2453,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         ea.win = buf[cur];
         ea.w = buf[cur ^ 1];
         prof_begin("edt1_y", s);
-        QAI_TRY(launch_env(1, false, ea, t1, s));
+        QAI_TRY(launch_env(1, ea, t1, s));
         prof_end(s);
         cur ^= 1;
     }
@@ -2474,7 +2461,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         ea.win = buf[cur];
         ea.w = buf[cur ^ 1];
         prof_begin("edt1_z", s);
-        QAI_TRY(launch_env(2, false, ea, t1, s));
+        QAI_TRY(launch_env(2, ea, t1, s));
         prof_end(s);
         cur ^= 1;
     }
@@ -2508,7 +2495,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         if (blk)
             QAI_TRY((launch_lane2_t<1, true>(ea, hb, s)));
         else
-            QAI_TRY(launch_env(1, false, ea, t, s));
+            QAI_TRY(launch_env(1, ea, t, s));
         prof_end(s);
         c2 = nx2;
     }
@@ -2528,7 +2515,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         ea.win = buf[c2];
         ea.w = buf[nx2];
         prof_begin("edt2_z", s);
-        QAI_TRY(launch_env(2, false, ea, t, s));
+        QAI_TRY(launch_env(2, ea, t, s));
         prof_end(s);
         c2 = nx2;
     }
