@@ -1034,8 +1034,8 @@ __global__ __launch_bounds__(64 * WPB) void k_env_swin(EnvArgs a)
                     pl = f;
                 }
             }
-            if (valid)
-                outb[(uint32_t)f * us + uc] = best;
+            // spare lanes of a partial tile read column x0 and store lane 0's value there
+            outb[(uint32_t)f * us + uc] = best;
         };
 
         uint32_t A[8], B[8];
@@ -1045,32 +1045,44 @@ __global__ __launch_bounds__(64 * WPB) void k_env_swin(EnvArgs a)
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             B[k] = inb[(uint32_t)min(8 + k, n - 1) * us + uc];
-        // block b: store rows 8b..8b+7 into the ring, prefetch block b+2, finalize block b-1
-        for (int b = 0; b < nb; b += 2) {
+        // block b: store rows 8b..8b+7 into the ring, prefetch block b+2, finalize
+        // block b-1 (its searches reach 8 rows into block b).  Pairs of blocks
+        // without guards (a guarded use of a prefetched block made the compiler
+        // wait for every outstanding load at the loop's back edge), then an odd
+        // last block.
+        auto ring_put = [&](int b, const uint32_t (&R)[8]) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                rl[(((b * 8) + k) & (RN - 1)) * 64] = A[k];
-                seen |= A[k] != QAI_WORD_INF;
-                sm = (A[k] != QAI_WORD_INF) ? (sm | (1u << (((b * 8) + k) & 31))) : (sm & ~(1u << (((b * 8) + k) & 31)));
+                rl[(((b * 8) + k) & (RN - 1)) * 64] = R[k];
+                seen |= R[k] != QAI_WORD_INF;
+                sm = (R[k] != QAI_WORD_INF) ? (sm | (1u << (((b * 8) + k) & 31))) : (sm & ~(1u << (((b * 8) + k) & 31)));
             }
+        };
+        int b = 0;
+        for (; b + 2 <= nb; b += 2) {
+            ring_put(b, A);
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 A[k] = inb[(uint32_t)min((b + 2) * 8 + k, n - 1) * us + uc];
-            if (b >= 1)
+            if (b >= 1) {
+#pragma unroll
                 for (int k = 0; k < 8; ++k)
                     finalize((b - 1) * 8 + k);
-            if (b + 1 < nb) {
+            }
+            ring_put(b + 1, B);
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    rl[(((b + 1) * 8 + k) & (RN - 1)) * 64] = B[k];
-                    seen |= B[k] != QAI_WORD_INF;
-                    sm = (B[k] != QAI_WORD_INF) ? (sm | (1u << (((b + 1) * 8 + k) & 31))) : (sm & ~(1u << (((b + 1) * 8 + k) & 31)));
-                }
+            for (int k = 0; k < 8; ++k)
+                B[k] = inb[(uint32_t)min((b + 3) * 8 + k, n - 1) * us + uc];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                finalize(b * 8 + k);
+        }
+        if (b < nb) {
+            ring_put(b, A);
+            if (b >= 1) {
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
-                    B[k] = inb[(uint32_t)min((b + 3) * 8 + k, n - 1) * us + uc];
-                for (int k = 0; k < 8; ++k)
-                    finalize(b * 8 + k);
+                    finalize((b - 1) * 8 + k);
             }
         }
         // the last block
