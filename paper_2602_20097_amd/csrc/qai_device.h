@@ -72,6 +72,18 @@ __device__ __forceinline__ int32_t recover_q(float x, float inv2eb, float two_eb
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also orders global
+// memory, which on this target waits for every outstanding global load and
+// store first: in a loop that prefetches rows from HBM it would wait for the
+// prefetch at every barrier.  Kernels whose barriers guard LDS buffers alone
+// (no global data passed between waves) use this one.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Highest set bit of m at or below lane (inclusive), or -1.
 __device__ __forceinline__ int highest_at_or_below(uint64_t m, int lane)
 {

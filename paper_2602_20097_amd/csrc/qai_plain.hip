@@ -260,14 +260,14 @@ __global__ __launch_bounds__(512) void k_seed_slab(SlabArgs A)
                     dst[r * nx + x] = in ? slab_key<MODE>(a, rb + x, bad) : 0;
             }
         };
-        __syncthreads();
+        lds_barrier();
         if (hz)
             stage(z0 - 1);
         stage(z0);
         for (int64_t z = z0; z < z1; ++z) {
             if (hz)
                 stage(z + 1);
-            __syncthreads();
+            lds_barrier();
             const int64_t y = y0 + wave;
             if (wave < A.ty && y < ny) {
                 const int rc = hy ? wave + 1 : 0;
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(512) void k_seed_slab(SlabArgs A)
                         next = c * 64 + __ffsll((unsigned long long)m) - 1;
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
         if (MODE == 0 && __ballot(bad) && lane == 0)
             atomicOr(a.status, QAI_STATUS_QRANGE);
@@ -426,24 +426,25 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_reg(SlabArgs A)
         const bool halo = hy && (wave == 0 || wave == WPB - 1);
         const int hrow = (wave == 0) ? 0 : R - 1;
 
-        auto load = [&](int64_t zz, int64_t yy, uint32_t (&r)[NCH]) {
-            if (zz >= 0 && zz < nz && yy >= 0 && yy < ny) {
-                const uint32_t* p = src + (zz * ny + yy) * (int64_t)nx;
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    const int x = c * 64 + lane;
-                    r[c] = (c + 1 < NCH || x < nx) ? p[x] : 0u;
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c)
-                    r[c] = 0u;
-            }
-        };
-        auto keys = [&](const uint32_t (&r)[NCH], int (&k)[NCH]) {
+        // Loads go to valid addresses without branching (a line outside the
+        // field reads line 0, a lane past the end of the line the last voxel);
+        // keys() substitutes 0 for them.  A branch here would leave the loaded
+        // registers to merge with zeros at its join, and the copy there waits
+        // for the loads: the prefetch would be lost.
+        auto load = [&](int64_t zz, int64_t yy, uint32_t (&r)[NCH]) -> bool {
+            const bool ok = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
+            const uint32_t* p = src + ((ok ? zz : 0) * ny + (ok ? yy : 0)) * (int64_t)nx;
 #pragma unroll
             for (int c = 0; c < NCH; ++c)
-                k[c] = reg_key<MODE>(r[c], a.inv2eb, a.two_eb, bad);
+                r[c] = p[c + 1 < NCH ? c * 64 + lane : min(c * 64 + lane, nx - 1)];
+            return ok;
+        };
+        auto keys = [&](const uint32_t (&r)[NCH], bool ok, int (&k)[NCH]) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const bool in = ok && (c + 1 < NCH || c * 64 + lane < nx);
+                k[c] = reg_key<MODE>(in ? r[c] : 0u, a.inv2eb, a.two_eb, bad);
+            }
         };
         auto put = [&](int b, int row, const int (&k)[NCH]) {
 #pragma unroll
@@ -453,25 +454,25 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_reg(SlabArgs A)
 
         uint32_t raw[NCH], hraw[NCH];
         int P0[NCH], P1[NCH], P2[NCH];
-        load(z0 - 1, y, raw);
-        keys(raw, P0);
-        load(z0, y, raw);
-        keys(raw, P1);
+        bool rok = load(z0 - 1, y, raw), hok = false;
+        keys(raw, rok, P0);
+        rok = load(z0, y, raw);
+        keys(raw, rok, P1);
         if (halo)
-            load(z0, yh, hraw);
-        load(z0 + 1, y, raw);
-        keys(raw, P2);
-        __syncthreads();
+            hok = load(z0, yh, hraw);
+        rok = load(z0 + 1, y, raw);
+        keys(raw, rok, P2);
+        lds_barrier();
         put(0, wave + 1, P1);
         if (halo) {
             int H[NCH];
-            keys(hraw, H);
+            keys(hraw, hok, H);
             put(0, hrow, H);
         }
-        load(z0 + 2, y, raw);
+        rok = load(z0 + 2, y, raw);
         if (halo)
-            load(z0 + 1, yh, hraw);
-        __syncthreads();
+            hok = load(z0 + 1, yh, hraw);
+        lds_barrier();
 
         int cur = 0;
         for (int64_t z = z0; z < z1; ++z) {
@@ -579,18 +580,18 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_reg(SlabArgs A)
                     P0[c] = P1[c];
                     P1[c] = P2[c];
                 }
-                keys(raw, P2);
+                keys(raw, rok, P2);
                 put(cur ^ 1, wave + 1, P1);
                 if (halo) {
                     int H[NCH];
-                    keys(hraw, H);
+                    keys(hraw, hok, H);
                     put(cur ^ 1, hrow, H);
                 }
-                load(z + 3, y, raw);
+                rok = load(z + 3, y, raw);
                 if (halo)
-                    load(z + 2, yh, hraw);
+                    hok = load(z + 2, yh, hraw);
             }
-            __syncthreads();
+            lds_barrier();
             cur ^= 1;
         }
     }
@@ -837,7 +838,7 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords)
     }
     if (lane == 63)
         wsum[wv] = incl;
-    __syncthreads();
+    lds_barrier();
     int before = 0, total = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -860,7 +861,7 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords)
                 ++p;
             }
         }
-        __syncthreads();
+        lds_barrier();
         const int cnt = min(L, total - w0);
 #pragma unroll 1
         for (int j = tid; j < cnt; j += 256) {
@@ -870,7 +871,7 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords)
             const uint32_t d2 = zsearch<BUF>(g, gy_index<BLK>(a, i), gplane, (int)(i / plane), (int)a.nz);
             a.out[i] = interp_at(a, i, w, xv, d2);
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
