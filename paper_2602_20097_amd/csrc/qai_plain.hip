@@ -667,6 +667,18 @@ __device__ __forceinline__ int64_t gy_index(const ZsArgs& a, int64_t i)
     const int64_t y = r / a.nx, x = r - y * a.nx;
     return ((z * ((a.ny + 3) >> 2) + (y >> 2)) * a.nx + x) * 4 + (y & 3);
 }
+// the same in 32 bits (fields of fewer than 2^29 voxels); z of voxel i comes along
+template <bool BLK>
+__device__ __forceinline__ uint32_t gy_index32(const ZsArgs& a, uint32_t i, int& z)
+{
+    const uint32_t nx = (uint32_t)a.nx, plane = (uint32_t)(a.nx * a.ny);
+    const uint32_t zz = i / plane, r = i - zz * plane;
+    z = (int)zz;
+    if (!BLK)
+        return i;
+    const uint32_t y = r / nx, x = r - y * nx;
+    return ((zz * (uint32_t)((a.ny + 3) >> 2) + (y >> 2)) * nx + x) * 4u + (y & 3u);
+}
 template <bool BLK>
 __device__ __forceinline__ int64_t gy_plane(const ZsArgs& a)
 {
@@ -690,6 +702,18 @@ struct GyReader {
             return __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)i * 4u, 0, 0);
         return gy[i];
     }
+    // word at index i where take, else QAI_WORD_INF.  With buffer loads the
+    // load is issued either way, at an offset past the buffer where it is not
+    // wanted (the hardware returns 0 there without a memory access): no branch,
+    // so several such loads stay in flight together.
+    __device__ __forceinline__ uint32_t at_if(bool take, int64_t i) const
+    {
+        if (BUF) {
+            const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, take ? (uint32_t)i * 4u : 0xFFFFFFF0u, 0, 0);
+            return take ? v : QAI_WORD_INF;
+        }
+        return take ? gy[i] : QAI_WORD_INF;
+    }
 };
 
 // Exact d2 at voxel i (plane z) from the y-pass words: the outward search
@@ -706,8 +730,8 @@ __device__ __forceinline__ uint32_t zsearch(const GyReader<BUF>& g, int64_t i, i
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int r = r0 + k;
-            lo[k] = (z - r >= 0) ? g.at(i - (int64_t)r * plane) : QAI_WORD_INF;
-            hi[k] = (z + r < nz) ? g.at(i + (int64_t)r * plane) : QAI_WORD_INF;
+            lo[k] = g.at_if(z - r >= 0, i - (int64_t)r * plane);
+            hi[k] = g.at_if(z + r < nz, i + (int64_t)r * plane);
         }
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -785,10 +809,16 @@ __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
             x[k] = i0 + k < n ? a.xq[i0 + k] : 0.0f;
         }
     }
+    // the y-pass word of each needed voxel, the four loads in flight together
     uint32_t gv[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        gv[k] = (word_sign(w[k]) != 0 && word_d2(w[k]) != 0u) ? g.at(gy_index<BLK>(a, i0 + k)) : QAI_WORD_INF;
+    for (int k = 0; k < 4; ++k) {
+        const bool nd = word_sign(w[k]) != 0 && word_d2(w[k]) != 0u;
+        int z;
+        const int64_t j = BUF ? (int64_t)gy_index32<BLK>(a, (uint32_t)min(i0 + k, n - 1), z)
+                              : gy_index<BLK>(a, min(i0 + k, n - 1));
+        gv[k] = g.at_if(nd, j);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         far[k] = !interp_near(a, i0 + k, w[k], x[k], gv[k], o[k]);
@@ -868,7 +898,11 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords)
             const int64_t i = list[j];
             const uint32_t w = a.w1[i];
             const float xv = a.xq[i];
-            const uint32_t d2 = zsearch<BUF>(g, gy_index<BLK>(a, i), gplane, (int)(i / plane), (int)a.nz);
+            int z;
+            const int64_t jg = BUF ? (int64_t)gy_index32<BLK>(a, (uint32_t)i, z) : gy_index<BLK>(a, i);
+            if (!BUF)
+                z = (int)(i / plane);
+            const uint32_t d2 = zsearch<BUF>(g, jg, gplane, z, (int)a.nz);
             a.out[i] = interp_at(a, i, w, xv, d2);
         }
         lds_barrier();
