@@ -135,6 +135,34 @@ def test_determinism_and_in_place():
     assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(a, u)
 
 
+def test_unaligned_field_and_out_take_the_whole_pass():
+    """A field or output not 16-byte aligned (a view at an odd storage offset)
+    runs the second EDT's whole z pass and step E instead of the needed-voxel
+    search; the output is the same bit for bit, also in place, and so are the
+    gradients the adjoint derives from the saved distance words."""
+    import paper_2602_20097_amd as qai
+    x32, xq, q, eb = synth.quantize(synth.grf((20, 36, 50), 3.0, 4242), 2e-2)
+    n = xq.size
+    t = torch.from_numpy(xq).cuda()
+    ws_a = qai.new_workspace(t.shape)
+    ref = qai.mitigate(t, eb, workspace=ws_a)
+    big = torch.empty(n + 8, dtype=torch.float32, device="cuda")
+    f = big[1:1 + n].view(t.shape)            # 4 bytes past a 16-byte boundary
+    f.copy_(t)
+    o = torch.empty(n + 8, dtype=torch.float32, device="cuda")[3:3 + n].view(t.shape)
+    ws_b = qai.new_workspace(t.shape)
+    got = qai.mitigate(f, eb, out=o, workspace=ws_b)
+    g = torch.randn_like(ref)
+    ga = qai.backward(g, ws_a, t.shape, eb)
+    gb = qai.backward(g, ws_b, t.shape, eb)
+    inplace = big[1:1 + n].view(t.shape)
+    qai.mitigate(inplace, eb, out=inplace)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    assert torch.equal(inplace, ref)
+    assert torch.equal(ga, gb)
+
+
 def test_status_flag_for_out_of_range_indices():
     import paper_2602_20097_amd as qai
     xq = np.zeros((4, 5, 6), np.float32)
