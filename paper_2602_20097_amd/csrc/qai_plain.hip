@@ -374,6 +374,176 @@ __global__ __launch_bounds__(512) void k_seed_slab(SlabArgs A)
     }
 }
 
+// Long x-lines (more than 512 voxels): one line per workgroup, its chunks of
+// 64 voxels split between the SEG wavefronts, so that a line's two sweeps
+// run in parallel pieces instead of one wave walking the whole line.  Sweep 1
+// (each wave over its own chunks): stencil and sites as k_seed_slab, the
+// chunk's site mask and codes, and the last site before each chunk within the
+// wave's piece.  After a barrier each wave takes the last site left of its
+// piece and the first one right of it from the other pieces' masks, then runs
+// sweep 2 over its chunks.  The ring holds the line and its two neighbour
+// lines of planes z-1, z, z+1; the block marches tz planes.
+template <int MODE, int SEG>
+__global__ __launch_bounds__(64 * SEG) void k_seed_seg(SlabArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SeedArgs& a = A.s;
+    const int nx = (int)a.nx;
+    const int64_t ny = a.ny, nz = a.nz;
+    const int wave = (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int nch = (nx + 63) >> 6;
+    const int c0 = (wave * nch) / SEG, c1 = ((wave + 1) * nch) / SEG;   // this wave's chunks
+    const size_t ring_bytes = ((size_t)A.planes * A.rows * nx * 4 + 15) & ~(size_t)15;
+    int* ring = (int*)smem;                                              // [plane][row][x]
+    unsigned char* codes = smem + ring_bytes;                            // [chunk][lane]
+    uint64_t* masks = (uint64_t*)(codes + (((size_t)nch * 64 + 15) & ~(size_t)15));
+    int* lastb = (int*)(masks + nch);                                    // last site before chunk, in the piece
+    const int64_t plane = (int64_t)nx * ny;
+    const bool hy = ny > 1, hz = nz > 1, hx = nx > 1;
+    const uint64_t nblocks = (uint64_t)(A.nby * A.nbz);
+
+    for (uint64_t t = blockIdx.x; t < nblocks; t += gridDim.x) {
+        const uint64_t bl = xcd_remap(t, nblocks);
+        const int64_t y = (int64_t)(bl % (uint64_t)A.nby), bz = (int64_t)(bl / (uint64_t)A.nby);
+        const int64_t z0 = bz * A.tz, z1 = min(nz, z0 + A.tz);
+        const int64_t ry0 = hy ? y - 1 : y; // y of ring row 0
+        bool bad = false;
+
+        auto stage = [&](int64_t zz) {
+            int* dst = ring + (int)((hz ? (zz + 3) % 3 : 0) * A.rows * nx);
+            for (int r = 0; r < A.rows; ++r) {
+                const int64_t yy = ry0 + r;
+                const bool in = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
+                const int64_t rb = zz * plane + yy * nx;
+                for (int x = threadIdx.x; x < nx; x += blockDim.x)
+                    dst[r * nx + x] = in ? slab_key<MODE>(a, rb + x, bad) : 0;
+            }
+        };
+        lds_barrier();
+        if (hz)
+            stage(z0 - 1);
+        stage(z0);
+        for (int64_t z = z0; z < z1; ++z) {
+            if (hz)
+                stage(z + 1);
+            lds_barrier();
+            const int rc = hy ? 1 : 0;
+            const int* pc = ring + (int)((hz ? z % 3 : 0) * A.rows * nx);
+            const int* pm = hz ? ring + (int)(((z + 2) % 3) * A.rows * nx) : pc;
+            const int* pp = hz ? ring + (int)(((z + 1) % 3) * A.rows * nx) : pc;
+            const int* rowc = pc + rc * nx;
+            const int* rowym = hy ? pc + (rc - 1) * nx : rowc;
+            const int* rowyp = hy ? pc + (rc + 1) * nx : rowc;
+            const int* rowzm = pm + rc * nx;
+            const int* rowzp = pp + rc * nx;
+            const bool line_in = (!hy || (y >= 1 && y <= ny - 2)) && (!hz || (z >= 1 && z <= nz - 2));
+            const int64_t base = (z * ny + y) * nx;
+            // sweep 1 over this wave's chunks
+            int last = -1;
+            for (int c = c0; c < c1; ++c) {
+                const int x = c * 64 + lane;
+                const bool valid = x < nx;
+                const int kc = valid ? rowc[x] : 0;
+                const bool x_in = !hx || (x >= 1 && x <= nx - 2);
+                bool site = false;
+                int sgn = 0;
+                if (valid && line_in && x_in) {
+                    const int kp = hx ? rowc[x + 1] : kc, km = hx ? rowc[x - 1] : kc;
+                    const int ky1 = rowyp[x], ky0 = rowym[x], kz1 = rowzp[x], kz0 = rowzm[x];
+                    if (MODE == 0) {
+                        // Algorithm 2 (as in k_seed_slab)
+                        int first = (kp != kc) ? kp - kc : ((km != kc) ? km - kc : 0);
+                        if (first == 0)
+                            first = (ky1 != kc) ? ky1 - kc : ((ky0 != kc) ? ky0 - kc : 0);
+                        if (first == 0)
+                            first = (kz1 != kc) ? kz1 - kc : ((kz0 != kc) ? kz0 - kc : 0);
+                        const bool steep = abs(kp - km) >= 2 || abs(ky1 - ky0) >= 2 || abs(kz1 - kz0) >= 2;
+                        if (first != 0) {
+                            site = true;
+                            sgn = steep ? 0 : (first > 0 ? 1 : -1);
+                        }
+                    } else {
+                        // Algorithm 3's GetBoundary(S) (as in k_seed_slab)
+                        const int sc = kc & 3;
+                        site = !(kc & 4) && (((kp & 3) != sc) || ((km & 3) != sc) || ((ky1 & 3) != sc) ||
+                                             ((ky0 & 3) != sc) || ((kz1 & 3) != sc) || ((kz0 & 3) != sc));
+                    }
+                }
+                if (MODE == 0)
+                    codes[c * 64 + lane] = (unsigned char)sign_code(sgn);
+                const uint64_t m = __ballot(site);
+                if (lane == 0) {
+                    masks[c] = m;
+                    lastb[c] = last;
+                }
+                if (m)
+                    last = c * 64 + 63 - __clzll(m);
+                if (valid) {
+                    const int64_t i = base + x;
+                    if (MODE == 0) {
+                        if (a.tq) a.tq[i] = kc;
+                        if (a.tb1) a.tb1[i] = site ? 1 : 0;
+                        if (a.tsb) a.tsb[i] = (int8_t)(site ? sgn : 0);
+                    } else {
+                        const int sg = (kc & 3) == 1 ? 1 : ((kc & 3) == 3 ? -1 : 0);
+                        if (a.ts) a.ts[i] = (int8_t)sg;
+                        if (a.td1) {
+                            const uint32_t w = a.w1[i];
+                            a.td1[i] = (w == QAI_WORD_INF) ? -1 : (int32_t)word_d2(w);
+                        }
+                        if (a.tb2) a.tb2[i] = site ? 1 : 0;
+                    }
+                }
+            }
+            lds_barrier();
+            // the nearest sites outside this wave's piece
+            int carry_l = -1, carry_r = -1;
+            for (int c = c0 - 1; c >= 0; --c) {
+                const uint64_t m = masks[c];
+                if (m) {
+                    carry_l = c * 64 + 63 - __clzll(m);
+                    break;
+                }
+            }
+            for (int c = c1; c < nch; ++c) {
+                const uint64_t m = masks[c];
+                if (m) {
+                    carry_r = c * 64 + __ffsll((unsigned long long)m) - 1;
+                    break;
+                }
+            }
+            // sweep 2 over this wave's chunks: nearest of the two, ties to the left site
+            int next = carry_r;
+            for (int c = c1 - 1; c >= c0; --c) {
+                const uint64_t m = masks[c];
+                const int lbc = lastb[c];
+                const int cl = lbc >= 0 ? lbc : carry_l;
+                const int x = c * 64 + lane;
+                const int hb = highest_at_or_below(m, lane);
+                const int lb = lowest_at_or_above(m, lane);
+                const int L = hb >= 0 ? c * 64 + hb : cl;
+                const int R = lb >= 0 ? c * 64 + lb : next;
+                uint32_t word = QAI_WORD_INF;
+                if (L >= 0 || R >= 0) {
+                    const int dl = L >= 0 ? x - L : 0x7fffffff;
+                    const int dr = R >= 0 ? R - x : 0x7fffffff;
+                    const int st = (dl <= dr) ? L : R;
+                    const uint32_t d = (uint32_t)(dl <= dr ? dl : dr);
+                    const uint32_t code = (MODE == 0) ? (uint32_t)codes[st] : 0u;
+                    word = word_make(d * d, code);
+                }
+                if (x < nx)
+                    a.wout[base + x] = word;
+                if (m)
+                    next = c * 64 + __ffsll((unsigned long long)m) - 1;
+            }
+            lds_barrier();
+        }
+        if (MODE == 0 && __ballot(bad) && lane == 0)
+            atomicOr(a.status, QAI_STATUS_QRANGE);
+    }
+}
+
 __device__ __forceinline__ int32_t raw_word_d1(const uint32_t* w1, int64_t i)
 {
     const uint32_t w = w1[i];
@@ -2170,6 +2340,30 @@ hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s, int want_ty,
         return mode == 0 ? launch_seed_reg<0>(in, tz, s) : launch_seed_reg<1>(in, tz, s);
     }
     const int planes = in.nz > 1 ? 3 : 1;
+    if (want_ty <= 0) {
+        // one line per workgroup, split over eight wavefronts
+        constexpr int SEG = 8;
+        const int rows = in.ny > 1 ? 3 : 1;
+        const int nch = (int)((in.nx + 63) / 64);
+        const size_t lds = (((size_t)planes * rows * in.nx * 4 + 15) & ~(size_t)15) +
+                           (((size_t)nch * 64 + 15) & ~(size_t)15) + (size_t)nch * 12;
+        if (lds <= 96 * 1024 && nch >= SEG) {
+            SlabArgs A;
+            A.s = in;
+            A.ty = 1;
+            A.rows = rows;
+            A.planes = planes;
+            A.tz = in.nz > 1 ? (want_tz > 0 ? want_tz : 16) : 1;
+            A.nby = in.ny;
+            A.nbz = (in.nz + A.tz - 1) / A.tz;
+            const uint32_t grid = grid_cap((uint64_t)(A.nby * A.nbz), 1u << 20);
+            if (mode == 0)
+                hipLaunchKernelGGL((k_seed_seg<0, SEG>), dim3(grid), dim3(64 * SEG), lds, s, A);
+            else
+                hipLaunchKernelGGL((k_seed_seg<1, SEG>), dim3(grid), dim3(64 * SEG), lds, s, A);
+            return hipGetLastError();
+        }
+    }
     int ty = want_ty > 0 ? want_ty : 4;
     if (in.ny == 1)
         ty = 1;

@@ -190,6 +190,23 @@ def test_headline_512_full_parity():
     assert np.abs(g["out"].astype(np.float64) - x32).max() <= (1 + 0.9) * eb * (1 + 1e-6)
 
 
+@pytest.mark.parametrize("shape", [(1, 40, 2000), (5, 7, 1100), (3, 9, 600), (1, 3, 4099)])
+def test_long_lines(shape):
+    """x-lines longer than 512 voxels: the seed passes split each line over
+    several wavefronts (default) or keep it in one (explicit rows per block);
+    both agree with the oracle."""
+    import paper_2602_20097_amd as qai
+    x32, xq, q, eb = synth.quantize(synth.grf(shape, 3.0, 900 + sum(shape)), 2e-2)
+    assert_parity(xq, eb, label=f"long lines {shape}")
+    base = qai.get_tuning()
+    try:
+        qai.set_tuning(seed_rows=2)
+        assert_parity(xq, eb, label=f"long lines {shape}, slab")
+    finally:
+        qai.set_tuning(None)
+    assert qai.get_tuning() == base
+
+
 def test_blocked_handoff_to_the_needed_voxel_search():
     """With the second EDT's y pass on the per-lane envelope and its z pass
     automatic, a call without taps hands the y result to the needed-voxel
