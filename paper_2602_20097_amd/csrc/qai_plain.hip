@@ -550,29 +550,26 @@ __device__ __forceinline__ int32_t raw_word_d1(const uint32_t* w1, int64_t i)
     return (w == QAI_WORD_INF) ? -1 : (int32_t)word_d2(w);
 }
 
-// Register-resident variant of the seed passes for lines of up to NCH * 64
-// voxels.  A workgroup of WPB wavefronts owns WPB adjacent x-lines (one per
-// wave) and marches them through tz planes.  Each wave keeps its own line of
-// planes z-1, z, z+1 in registers (the +-z neighbours), the current plane's
-// lines of the group and its two halo lines sit in LDS (the +-x, +-y
-// neighbours; double-buffered, one barrier per plane), and the site masks of
-// the x-scan stay in scalar registers.
-template <int MODE>
-__device__ __forceinline__ int reg_key(uint32_t raw, float inv2eb, float two_eb, bool& bad)
+// Seed passes for lines of up to 64 * V voxels, lane l of a wave owning voxels
+// [V l, V l + V) of its line.  A workgroup of WPB wavefronts owns WPB adjacent
+// x-lines (one per wave) and marches them through tz planes.  Each wave keeps
+// its own line of planes z-1, z, z+1 in registers (the +-z neighbours); the
+// current plane's lines of the group and its two halo lines sit in LDS (the
+// +-y neighbours; double-buffered, one barrier per plane).  The +-x neighbours
+// are the lane's own registers except at its two ends.  The x pass of the EDT
+// needs no per-voxel masks: each lane scans its own voxels in order (nearest
+// site at or before, at or after) and takes one carry per direction from the
+// nearest lane holding a site.  Lines are
+// read and written VW words per access (VW divides V and nx).  LDS lines are
+// lane-major: voxel V l + j at j * 64 + l, so every LDS access of a wave is
+// 64 consecutive words.
+template <int MODE, int V, int WPB, int VW, bool TAPS>
+__global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
 {
-    if (MODE == 0)
-        return recover_q(__uint_as_float(raw), inv2eb, two_eb, bad);
-    const int sgn = word_sign(raw);
-    const int b1 = (raw != QAI_WORD_INF && word_d2(raw) == 0u) ? 4 : 0;
-    return (sgn & 3) | b1;
-}
-
-template <int MODE, int NCH, int WPB, bool TAPS>
-__global__ __launch_bounds__(64 * WPB) void k_seed_reg(SlabArgs A)
-{
-    constexpr int W = NCH * 64;          // LDS line pitch
-    constexpr int R = WPB + 2;           // lines per LDS plane (with the two halo lines)
-    __shared__ int rows[2][R * W];
+    static_assert(V % VW == 0, "vector width must divide the voxels per lane");
+    constexpr int W = V * 64;
+    constexpr int R = WPB + 2;
+    __shared__ uint32_t rows[2][R * W];
     const SeedArgs& a = A.s;
     const int nx = (int)a.nx;
     const int64_t ny = a.ny, nz = a.nz;
@@ -580,10 +577,19 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_reg(SlabArgs A)
     const int lane = threadIdx.x & 63;
     const bool hy = ny > 1, hz = nz > 1, hx = nx > 1;
     const uint32_t* __restrict__ src = (MODE == 0) ? (const uint32_t*)a.xq : a.w1;
-    const uint64_t below = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-    const uint64_t above = ~0ull << lane;
+    const int x0 = V * lane;               // first voxel of the lane
+    // stencil range along x: the interior when the axis exists
+    const int xmax = hx ? nx - 2 : nx - 1;
+    const bool first_in = x0 >= (hx ? 1 : 0);
+    const uint64_t lower = (1ull << lane) - 1ull;                        // lanes strictly below
+    const uint64_t upper = (lane == 63) ? 0ull : (~0ull << (lane + 1));  // strictly above
     const uint64_t nblocks = (uint64_t)(A.nby * A.nbz);
     bool bad = false;
+
+    // Site value of voxel x with payload code: ((x + 4096) << 2) | code, so
+    // values order like positions.  "No site" to the left is 0, to the right
+    // NONE_R; either lies more than 4096 voxels away.
+    constexpr uint32_t NONE_R = (8191u + 4096u) << 2;
 
     for (uint64_t t = blockIdx.x; t < nblocks; t += gridDim.x) {
         const uint64_t bl = xcd_remap(t, nblocks);
@@ -591,39 +597,58 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_reg(SlabArgs A)
         const int64_t y0 = by * WPB, z0 = bz * A.tz;
         const int64_t z1 = min(nz, z0 + A.tz);
         const int64_t y = y0 + wave;
-        // the halo lines are read by the first and last wave
         const int64_t yh = (wave == 0) ? y0 - 1 : y0 + WPB;
         const bool halo = hy && (wave == 0 || wave == WPB - 1);
         const int hrow = (wave == 0) ? 0 : R - 1;
 
-        // Loads go to valid addresses without branching (a line outside the
-        // field reads line 0, a lane past the end of the line the last voxel);
-        // keys() substitutes 0 for them.  A branch here would leave the loaded
-        // registers to merge with zeros at its join, and the copy there waits
-        // for the loads: the prefetch would be lost.
-        auto load = [&](int64_t zz, int64_t yy, uint32_t (&r)[NCH]) -> bool {
+        // Loads go to valid addresses without branching: a line outside the
+        // field reads line 0 and a group of words past the end of the line the
+        // line's first group; keys() substitutes 0 for them (nx is a multiple
+        // of VW: a group lies wholly inside or outside).  A branch here would
+        // leave the loaded registers to merge with zeros at its join, and the
+        // copy there waits for the loads: the prefetch would be lost.
+        auto load = [&](int64_t zz, int64_t yy, uint32_t (&r)[V]) -> bool {
             const bool ok = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
             const uint32_t* p = src + ((ok ? zz : 0) * ny + (ok ? yy : 0)) * (int64_t)nx;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                r[c] = p[c + 1 < NCH ? c * 64 + lane : min(c * 64 + lane, nx - 1)];
+            for (int j = 0; j < V; j += VW) {
+                const uint32_t* q = p + (x0 + j < nx ? x0 + j : 0);
+                if (VW == 4) {
+                    const uint4 v = *(const uint4*)q;
+                    r[j] = v.x, r[j + 1] = v.y, r[j + 2] = v.z, r[j + 3] = v.w;
+                } else if (VW == 2) {
+                    const uint2 v = *(const uint2*)q;
+                    r[j] = v.x, r[j + 1] = v.y;
+                } else {
+                    r[j] = *q;
+                }
+            }
             return ok;
         };
-        auto keys = [&](const uint32_t (&r)[NCH], bool ok, int (&k)[NCH]) {
+        // Keys: mode 0 the quantization index with its sign bit flipped (the
+        // unsigned order of the keys is then the signed order of q); mode 1
+        // the sign code of the first-EDT word (0: S = 0, 1: +1, 2: -1; 3 for
+        // "no site", which occurs only when B1 is empty, everywhere at once)
+        // plus 4 on B1 (distance 0).
+        auto keys = [&](const uint32_t (&r)[V], bool ok, uint32_t (&k)[V]) {
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const bool in = ok && (c + 1 < NCH || c * 64 + lane < nx);
-                k[c] = reg_key<MODE>(in ? r[c] : 0u, a.inv2eb, a.two_eb, bad);
+            for (int j = 0; j < V; ++j) {
+                const bool in = ok && x0 + j < nx;
+                const uint32_t w = in ? r[j] : 0u;
+                if (MODE == 0)
+                    k[j] = (uint32_t)recover_q(__uint_as_float(w), a.inv2eb, a.two_eb, bad) ^ 0x80000000u;
+                else
+                    k[j] = (w & 3u) | (w < 4u ? 4u : 0u);
             }
         };
-        auto put = [&](int b, int row, const int (&k)[NCH]) {
+        auto put = [&](int b, int row, const uint32_t (&k)[V]) {
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                rows[b][row * W + c * 64 + lane] = k[c];
+            for (int j = 0; j < V; ++j)
+                rows[b][row * W + j * 64 + lane] = k[j];
         };
 
-        uint32_t raw[NCH], hraw[NCH];
-        int P0[NCH], P1[NCH], P2[NCH];
+        uint32_t raw[V], hraw[V];
+        uint32_t P0[V], P1[V], P2[V];
         bool rok = load(z0 - 1, y, raw), hok = false;
         keys(raw, rok, P0);
         rok = load(z0, y, raw);
@@ -632,10 +657,16 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_reg(SlabArgs A)
             hok = load(z0, yh, hraw);
         rok = load(z0 + 1, y, raw);
         keys(raw, rok, P2);
+        if (!hz) {
+            // a flat z axis: the +-z neighbours are the voxel itself
+#pragma unroll
+            for (int j = 0; j < V; ++j)
+                P0[j] = P2[j] = P1[j];
+        }
         lds_barrier();
         put(0, wave + 1, P1);
         if (halo) {
-            int H[NCH];
+            uint32_t H[V];
             keys(hraw, hok, H);
             put(0, hrow, H);
         }
@@ -647,113 +678,122 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_reg(SlabArgs A)
         int cur = 0;
         for (int64_t z = z0; z < z1; ++z) {
             if (y < ny) {
-                const int* rc = &rows[cur][(wave + 1) * W];
-                const int* rym = hy ? rc - W : rc;
-                const int* ryp = hy ? rc + W : rc;
+                const uint32_t* rc = &rows[cur][(wave + 1) * W];
+                const uint32_t* rym = hy ? rc - W : rc;
+                const uint32_t* ryp = hy ? rc + W : rc;
                 const bool line_in = (!hy || (y >= 1 && y <= ny - 2)) && (!hz || (z >= 1 && z <= nz - 2));
-                // sweep 1 (right to left): stencil, site mask, and per lane the
-                // nearest site at or after it (distance <= 1023 or none) with its
-                // code, plus the highest site at or below it inside the chunk;
-                // packed: dr | codeR << 10 | (bl + 1) << 12 | codeL << 19
-                uint32_t pk[NCH];
-                uint32_t lastp[NCH]; // per chunk: (highest site + 1) | its code << 16, 0 if none
-                int first = -1, fc = 0;
+                // the neighbours across the lane's two ends (a flat x axis: itself)
+                const uint32_t kleft = hx ? rc[(V - 1) * 64 + (lane > 0 ? lane - 1 : 0)] : P1[0];
+                const uint32_t kright = hx ? rc[lane < 63 ? lane + 1 : 63] : P1[V - 1];
+                bool st[V];      // voxel x0 + j is a site
+                uint32_t sv[V];  // its site value
 #pragma unroll
-                for (int c = NCH - 1; c >= 0; --c) {
-                    const int x = c * 64 + lane;
-                    const int kc = P1[c];
-                    const int kxp = hx ? rc[min(x + 1, W - 1)] : kc;
-                    const int kxm = hx ? rc[max(x - 1, 0)] : kc;
-                    const int kyp = ryp[x], kym = rym[x];
-                    const int kzp = hz ? P2[c] : kc, kzm = hz ? P0[c] : kc;
-                    const bool in = line_in && (c + 1 < NCH || x < nx) && (!hx || (x >= 1 && x <= nx - 2));
-                    bool site;
-                    int sgn = 0;
+                for (int j = 0; j < V; ++j) {
+                    const int x = x0 + j;
+                    const uint32_t kc = P1[j];
+                    const uint32_t kxp = j + 1 < V ? P1[j + 1] : kright;
+                    const uint32_t kxm = j > 0 ? P1[j - 1] : kleft;
+                    const uint32_t kyp = ryp[j * 64 + lane], kym = rym[j * 64 + lane];
+                    const uint32_t kzp = P2[j], kzm = P0[j];
+                    const bool in = line_in && x <= xmax && (j > 0 || first_in);
+                    uint32_t code = 0u;
                     if (MODE == 0) {
-                        // Algorithm 2 (see k_seed_slab)
-                        int f = (kxp != kc) ? kxp - kc : ((kxm != kc) ? kxm - kc : 0);
-                        if (f == 0)
-                            f = (kyp != kc) ? kyp - kc : ((kym != kc) ? kym - kc : 0);
-                        if (f == 0)
-                            f = (kzp != kc) ? kzp - kc : ((kzm != kc) ? kzm - kc : 0);
-                        const bool steep =
-                            abs(kxp - kxm) >= 2 || abs(kyp - kym) >= 2 || abs(kzp - kzm) >= 2;
-                        site = in && f != 0;
-                        sgn = (site && !steep) ? (f > 0 ? 1 : -1) : 0;
-                    } else {
-                        const int sc = kc & 3;
-                        site = in && !(kc & 4) &&
-                               (((kxp & 3) != sc) || ((kxm & 3) != sc) || ((kyp & 3) != sc) || ((kym & 3) != sc) ||
-                                ((kzp & 3) != sc) || ((kzm & 3) != sc));
-                    }
-                    const uint64_t m = __ballot(site);
-                    const int code = (int)sign_code(sgn);
-                    if (TAPS && x < nx) {
-                        const int64_t i = (z * ny + y) * (int64_t)nx + x;
-                        if (MODE == 0) {
-                            if (a.tq) a.tq[i] = kc;
-                            if (a.tb1) a.tb1[i] = site ? 1 : 0;
+                        // Algorithm 2 (see k_seed_slab): g is the first neighbour that
+                        // differs from the voxel, in the order +x, -x, +y, -y, +z, -z
+                        uint32_t g = (kxp != kc) ? kxp : kxm;
+                        g = (g != kc) ? g : ((kyp != kc) ? kyp : kym);
+                        g = (g != kc) ? g : ((kzp != kc) ? kzp : kzm);
+                        // some axis differs by 2 or more: kp - km is not in {-1, 0, 1},
+                        // i.e. kp - km + 1 (mod 2^32) exceeds 2
+                        const bool steep = (kxp - kxm + 1u > 2u) | (kyp - kym + 1u > 2u) | (kzp - kzm + 1u > 2u);
+                        st[j] = in && g != kc;
+                        code = steep ? 0u : (g > kc ? 1u : 2u);
+                        if (TAPS && x < nx) {
+                            const int64_t i = (z * ny + y) * (int64_t)nx + x;
+                            const int sgn = st[j] ? (code == 1u ? 1 : (code == 2u ? -1 : 0)) : 0;
+                            if (a.tq) a.tq[i] = (int32_t)(kc ^ 0x80000000u);
+                            if (a.tb1) a.tb1[i] = st[j] ? 1 : 0;
                             if (a.tsb) a.tsb[i] = (int8_t)sgn;
-                        } else {
-                            if (a.ts) a.ts[i] = (int8_t)((kc & 3) == 1 ? 1 : ((kc & 3) == 3 ? -1 : 0));
+                        }
+                    } else {
+                        // Algorithm 3's GetBoundary(S) (see k_seed_slab)
+                        const uint32_t diff = (kxp ^ kc) | (kxm ^ kc) | (kyp ^ kc) | (kym ^ kc) | (kzp ^ kc) | (kzm ^ kc);
+                        st[j] = in && !(kc & 4u) && (diff & 3u) != 0u;
+                        if (TAPS && x < nx) {
+                            const int64_t i = (z * ny + y) * (int64_t)nx + x;
+                            if (a.ts) a.ts[i] = (int8_t)((kc & 3u) == 1u ? 1 : ((kc & 3u) == 2u ? -1 : 0));
                             if (a.td1) a.td1[i] = raw_word_d1(a.w1, i);
-                            if (a.tb2) a.tb2[i] = site ? 1 : 0;
+                            if (a.tb2) a.tb2[i] = st[j] ? 1 : 0;
                         }
                     }
-                    const uint64_t ml = m & below, mr = m & above;
-                    const int bl = ml ? 63 - __clzll(ml) : -1;
-                    const int br = mr ? __ffsll((unsigned long long)mr) - 1 : -1;
-                    // every lane takes part in the shuffles (source lanes must be active)
-                    const int cl = (MODE == 0) ? __shfl(code, bl & 63) : 0;
-                    const int cr = (MODE == 0) ? __shfl(code, br & 63) : 0;
-                    const int R = br >= 0 ? c * 64 + br : first;
-                    const int dr = R >= 0 ? R - x : 1023;
-                    const int crr = br >= 0 ? cr : fc;
-                    pk[c] = (uint32_t)dr | ((uint32_t)crr << 10) | ((uint32_t)(bl + 1) << 12) | ((uint32_t)cl << 19);
-                    lastp[c] = 0u;
-                    if (m) {
-                        const int hb = 63 - __clzll(m), lb = __ffsll((unsigned long long)m) - 1;
-                        lastp[c] = (uint32_t)(c * 64 + hb + 1) | ((uint32_t)((MODE == 0) ? __shfl(code, hb) : 0) << 16);
-                        first = c * 64 + lb;
-                        if (MODE == 0)
-                            fc = __shfl(code, lb);
-                    }
+                    sv[j] = ((uint32_t)(x + 4096) << 2) | code;
                 }
-                // sweep 2 (left to right): nearest of the two, ties to the left site
-                uint32_t* const wrow = a.wout + (z * ny + y) * (int64_t)nx;
-                uint32_t carry = 0u; // (last site before the chunk + 1) | code << 16
+                // nearest site at or before / at or after each voxel among the
+                // lane's own, then the carries: the last site of the nearest lane
+                // below holding one, the first of the nearest lane above (a value
+                // from below is smaller than any own one, from above larger)
+                uint32_t lv[V], rv[V];
+                uint32_t L = 0u, Rr = NONE_R;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    const int x = c * 64 + lane;
-                    const uint32_t v = pk[c];
-                    const int dr = (int)(v & 1023u);
-                    const int bl = (int)((v >> 12) & 127u) - 1;
-                    const int L = bl >= 0 ? c * 64 + bl : (int)(carry & 0xFFFFu) - 1;
-                    const int dl = L >= 0 ? x - L : 1023;
-                    uint32_t word = QAI_WORD_INF;
-                    if (dl < 1023 || dr < 1023) {
-                        const bool left = dl <= dr;
-                        const uint32_t d = (uint32_t)(left ? dl : dr);
-                        const uint32_t cd =
-                            left ? (bl >= 0 ? ((v >> 19) & 3u) : (carry >> 16)) : ((v >> 10) & 3u);
-                        word = word_make(d * d, (MODE == 0) ? cd : 0u);
+                for (int j = 0; j < V; ++j) {
+                    L = st[j] ? sv[j] : L;
+                    lv[j] = L;
+                }
+#pragma unroll
+                for (int j = V - 1; j >= 0; --j) {
+                    Rr = st[j] ? sv[j] : Rr;
+                    rv[j] = Rr;
+                }
+                const uint64_t m = __ballot(lv[V - 1] != 0u);
+                const uint64_t ml = m & lower, mr = m & upper;
+                const int sl = ml ? 63 - __clzll(ml) : 0;
+                const int sr = mr ? __ffsll((unsigned long long)mr) - 1 : 0;
+                const uint32_t cl = (uint32_t)__shfl((int)lv[V - 1], sl);
+                const uint32_t cr = (uint32_t)__shfl((int)rv[0], sr);
+                const uint32_t carry_l = ml ? cl : 0u, carry_r = mr ? cr : NONE_R;
+                uint32_t word[V];
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    // sweep result: nearest of the two, ties to the left site;
+                    // distances in units of 4 (d4 = 4 d, d4^2 / 4 = d^2 << 2)
+                    const uint32_t Lj = max(lv[j], carry_l), Rj = min(rv[j], carry_r);
+                    const uint32_t xb4 = (uint32_t)(x0 + j + 4096) << 2;
+                    const uint32_t cm = (MODE == 0) ? ~3u : ~0u; // mode 1 values carry no code
+                    const uint32_t dl4 = xb4 - (Lj & cm), dr4 = (Rj & cm) - xb4;
+                    const bool left = dl4 <= dr4;
+                    const uint32_t d4 = left ? dl4 : dr4;
+                    const uint32_t cd = (MODE == 0) ? ((left ? Lj : Rj) & 3u) : 0u;
+                    word[j] = (__umul24(d4, d4) >> 2) | cd;
+                }
+                if (m == 0ull) {
+                    // no site on the line
+#pragma unroll
+                    for (int j = 0; j < V; ++j)
+                        word[j] = QAI_WORD_INF;
+                }
+                uint32_t* const wrow = a.wout + (z * ny + y) * (int64_t)nx + x0;
+#pragma unroll
+                for (int j = 0; j < V; j += VW) {
+                    if (x0 + j < nx) {
+                        if (VW == 4)
+                            *(uint4*)(wrow + j) = make_uint4(word[j], word[j + 1], word[j + 2], word[j + 3]);
+                        else if (VW == 2)
+                            *(uint2*)(wrow + j) = make_uint2(word[j], word[j + 1]);
+                        else
+                            wrow[j] = word[j];
                     }
-                    if (c + 1 < NCH || x < nx)
-                        wrow[x] = word;
-                    if (lastp[c])
-                        carry = lastp[c];
                 }
             }
             if (z + 1 < z1) {
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    P0[c] = P1[c];
-                    P1[c] = P2[c];
+                for (int j = 0; j < V; ++j) {
+                    P0[j] = P1[j];
+                    P1[j] = P2[j];
                 }
                 keys(raw, rok, P2);
                 put(cur ^ 1, wave + 1, P1);
                 if (halo) {
-                    int H[NCH];
+                    uint32_t H[V];
                     keys(hraw, hok, H);
                     put(cur ^ 1, hrow, H);
                 }
@@ -2295,11 +2335,12 @@ static size_t slab_bytes(int64_t nx, int ty, int rows, int planes)
     return ring + (size_t)ty * nch * (64 + 8 + 4) + 64;
 }
 
-template <int MODE, int NCH>
-static hipError_t launch_seed_reg_t(const SeedArgs& in, int tz, hipStream_t s)
+template <int MODE, int V>
+static hipError_t launch_seed_lane_t(const SeedArgs& in, int tz, hipStream_t s)
 {
     const bool taps = (MODE == 0) ? (in.tq || in.tb1 || in.tsb) : (in.ts || in.td1 || in.tb2);
     constexpr int WPB = 8;
+    constexpr int VW4 = (V % 4 == 0) ? 4 : 1, VW2 = (V % 2 == 0) ? 2 : 1;
     SlabArgs A;
     A.s = in;
     A.ty = WPB;
@@ -2309,25 +2350,31 @@ static hipError_t launch_seed_reg_t(const SeedArgs& in, int tz, hipStream_t s)
     A.nby = (in.ny + WPB - 1) / WPB;
     A.nbz = (in.nz + tz - 1) / tz;
     const uint32_t grid = grid_cap((uint64_t)(A.nby * A.nbz), 1u << 20);
+    const uintptr_t al = (uintptr_t)((MODE == 0) ? (const void*)in.xq : (const void*)in.w1) | (uintptr_t)in.wout;
+    const dim3 g(grid), b(64 * WPB);
     if (taps)
-        hipLaunchKernelGGL((k_seed_reg<MODE, NCH, WPB, true>), dim3(grid), dim3(64 * WPB), 0, s, A);
+        hipLaunchKernelGGL((k_seed_lane<MODE, V, WPB, 1, true>), g, b, 0, s, A);
+    else if (V % 4 == 0 && in.nx % 4 == 0 && al % 16 == 0)
+        hipLaunchKernelGGL((k_seed_lane<MODE, V, WPB, VW4, false>), g, b, 0, s, A);
+    else if (V % 2 == 0 && in.nx % 2 == 0 && al % 8 == 0)
+        hipLaunchKernelGGL((k_seed_lane<MODE, V, WPB, VW2, false>), g, b, 0, s, A);
     else
-        hipLaunchKernelGGL((k_seed_reg<MODE, NCH, WPB, false>), dim3(grid), dim3(64 * WPB), 0, s, A);
+        hipLaunchKernelGGL((k_seed_lane<MODE, V, WPB, 1, false>), g, b, 0, s, A);
     return hipGetLastError();
 }
 
 template <int MODE>
-static hipError_t launch_seed_reg(const SeedArgs& in, int tz, hipStream_t s)
+static hipError_t launch_seed_lane(const SeedArgs& in, int tz, hipStream_t s)
 {
     switch ((int)((in.nx + 63) / 64)) {
-    case 1: return launch_seed_reg_t<MODE, 1>(in, tz, s);
-    case 2: return launch_seed_reg_t<MODE, 2>(in, tz, s);
-    case 3: return launch_seed_reg_t<MODE, 3>(in, tz, s);
-    case 4: return launch_seed_reg_t<MODE, 4>(in, tz, s);
-    case 5: return launch_seed_reg_t<MODE, 5>(in, tz, s);
-    case 6: return launch_seed_reg_t<MODE, 6>(in, tz, s);
-    case 7: return launch_seed_reg_t<MODE, 7>(in, tz, s);
-    default: return launch_seed_reg_t<MODE, 8>(in, tz, s);
+    case 1: return launch_seed_lane_t<MODE, 1>(in, tz, s);
+    case 2: return launch_seed_lane_t<MODE, 2>(in, tz, s);
+    case 3: return launch_seed_lane_t<MODE, 3>(in, tz, s);
+    case 4: return launch_seed_lane_t<MODE, 4>(in, tz, s);
+    case 5: return launch_seed_lane_t<MODE, 5>(in, tz, s);
+    case 6: return launch_seed_lane_t<MODE, 6>(in, tz, s);
+    case 7: return launch_seed_lane_t<MODE, 7>(in, tz, s);
+    default: return launch_seed_lane_t<MODE, 8>(in, tz, s);
     }
 }
 
@@ -2337,7 +2384,7 @@ hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s, int want_ty,
         return launch_seed_lines(mode, in, s); // one x-line per wave, neighbours through the caches
     if (in.nx <= 512 && want_ty <= 0) {
         const int tz = in.nz > 1 ? (want_tz > 0 ? want_tz : 16) : 1;
-        return mode == 0 ? launch_seed_reg<0>(in, tz, s) : launch_seed_reg<1>(in, tz, s);
+        return mode == 0 ? launch_seed_lane<0>(in, tz, s) : launch_seed_lane<1>(in, tz, s);
     }
     const int planes = in.nz > 1 ? 3 : 1;
     if (want_ty <= 0) {

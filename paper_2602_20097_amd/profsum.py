@@ -25,15 +25,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # kernel symbol -> bench stage (the plain path launches one kernel per stage)
 STAGES = [
-    (r"k_seed_(reg|slab|xscan|lines)<0", "seed1_xscan"),
-    (r"k_seed_(reg|slab|xscan|lines)<1", "seed2_xscan"),
+    (r"k_seed_(lane|seg|slab|xscan|lines)<0", "seed1_xscan"),
+    (r"k_seed_(lane|seg|slab|xscan|lines)<1", "seed2_xscan"),
     (r"k_interp_(own|far)", "edt2_z_interp"),
     (r"k_interp\b", "interp"),
     (r"k_copy", "copy_probe"),
     (r"k_clear", "clear"),
 ]
-SEED1 = r"k_seed_(reg|slab|xscan|lines)<0"
-SEED2 = r"k_seed_(reg|slab|xscan|lines)<1"
+SEED1 = r"k_seed_(lane|seg|slab|xscan|lines)<0"
+SEED2 = r"k_seed_(lane|seg|slab|xscan|lines)<1"
 
 
 def kernel_rev():
