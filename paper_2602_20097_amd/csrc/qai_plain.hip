@@ -1048,15 +1048,44 @@ __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
     }
 }
 
-// A block takes the four flag words of 64 waves of k_interp_own, spaced
-// gridDim.x waves apart: flagged voxels gather in places (along B2, and on
-// the two z faces, where B2 never lies, nearly every needed voxel is
-// flagged), and the spacing spreads such places over many blocks.  The
-// block's flagged voxels are listed in LDS (block-wide prefix sum of the word
-// popcounts) and dealt one per thread; lists longer than the LDS window go in
-// several rounds.
+// Which waves of k_interp_own a block of k_interp_far takes.  Searches of
+// voxels in the same (y, x) column and nearby planes read the same y-pass
+// lines, so where a plane holds whole waves (nx ny a multiple of 256) a block
+// takes 8 consecutive waves (whole rows) of 8 consecutive planes, and the
+// blocks run on each XCD (block b on XCD b % 8) walk a column group through a
+// quarter of the planes in order: the lines they read stay in that XCD's L2.
+// Column groups are dealt to the XCDs from both y faces inward, a quarter of
+// the planes per XCD: the face rows, where B2 never lies and every needed
+// voxel is flagged, are spread over all eight and taken first.  Otherwise a
+// block takes 64 waves spaced gridDim.x apart.
+struct FarMap {
+    int64_t wpp;          // waves per plane (0: the spaced mapping)
+    int64_t pb, zb, zbq;  // 8-wave groups per plane, 8-plane groups, 8-plane groups per quarter
+};
+
+__device__ __forceinline__ int64_t far_wave(const FarMap& f, int64_t nz, int64_t nwaves, int lw)
+{
+    if (f.wpp == 0) {
+        const int64_t w = (int64_t)blockIdx.x + (int64_t)lw * gridDim.x;
+        return w < nwaves ? w : -1;
+    }
+    const int k = blockIdx.x & 7;
+    const int64_t u = blockIdx.x >> 3;
+    const int64_t j = 2 * (u / f.zbq) + (k >> 2);
+    const int64_t zb = (k & 3) * f.zbq + u % f.zbq;
+    if (j >= f.pb || zb >= f.zb)
+        return -1;
+    const int64_t cg = (j & 1) ? f.pb - 1 - (j >> 1) : (j >> 1);
+    const int64_t z = zb * 8 + (lw >> 3), p = cg * 8 + (lw & 7);
+    return (z < nz && p < f.wpp) ? z * f.wpp + p : -1;
+}
+
+// A block takes the four flag words of 64 waves of k_interp_own (far_wave).
+// The block's flagged voxels are listed in LDS (block-wide prefix sum of the
+// word popcounts) and dealt one per thread; lists longer than the LDS window
+// go in several rounds.
 template <bool BUF, bool BLK>
-__global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords)
+__global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords, FarMap fm)
 {
     constexpr int L = 1024;
     __shared__ int64_t list[L];
@@ -1064,9 +1093,9 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords)
     const int64_t plane = a.nx * a.ny, gplane = gy_plane<BLK>(a);
     const GyReader<BUF> g(a.gy, gplane * a.nz);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t grp = (int64_t)blockIdx.x + (int64_t)(tid >> 2) * gridDim.x; // wave of k_interp_own
+    const int64_t grp = far_wave(fm, a.nz, nwords / 4, tid >> 2); // wave of k_interp_own
     const int64_t wi = grp * 4 + (tid & 3);
-    const uint64_t m = wi < nwords ? a.flags[wi] : 0ull;
+    const uint64_t m = grp >= 0 ? a.flags[wi] : 0ull;
     const int c = __popcll(m);
     // exclusive prefix of c over the block
     int incl = c;
@@ -1127,7 +1156,17 @@ static hipError_t launch_interp_search_t(const ZsArgs& a, int64_t blocks, hipStr
     if (e != hipSuccess)
         return e;
     const int64_t nwords = blocks * 16; // flag_bytes(n) / 8
-    hipLaunchKernelGGL((k_interp_far<BUF, BLK>), dim3((unsigned)((nwords / 4 + 63) / 64)), dim3(256), 0, s, a, nwords);
+    const int64_t plane = a.nx * a.ny;
+    FarMap fm{0, 0, 0, 0};
+    int64_t grid = (nwords / 4 + 63) / 64;
+    if (plane % 256 == 0) {
+        fm.wpp = plane / 256;
+        fm.pb = (fm.wpp + 7) / 8;
+        fm.zb = (a.nz + 7) / 8;
+        fm.zbq = (fm.zb + 3) / 4;
+        grid = 8 * ((fm.pb + 1) / 2) * fm.zbq;
+    }
+    hipLaunchKernelGGL((k_interp_far<BUF, BLK>), dim3((unsigned)grid), dim3(256), 0, s, a, nwords, fm);
     return hipGetLastError();
 }
 
