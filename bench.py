@@ -30,11 +30,13 @@ METRIC = "QAI post-pass GB/s of FP32 field and % HBM roofline, plain vs batched,
 HBM_PEAK_GBPS = 8000.0
 
 # Algorithmic HBM bytes per voxel of each stage (reads + writes of the
-# arrays the stage must touch once): the post-pass moves 52 B/voxel in 3-D.
+# arrays the stage must touch once): the post-pass moves 44 B/voxel in 3-D.
 STAGE_BYTES = {
     "seed1_xscan": 8,     # read x', write first-EDT words
     "edt1_y": 8,          # read + write words
     "edt1_z": 8,
+    "edt1_yz": 8,         # 3-D: both passes as one search (read x-pass words, write final words)
+    "edt1_fallback": 0,   # separable passes behind it, run only when a distance exceeds its disc
     "seed2_xscan": 8,     # read first-EDT words, write second-EDT words
     "edt2_y": 8,
     "edt2_z": 8,

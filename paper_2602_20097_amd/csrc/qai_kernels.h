@@ -37,7 +37,13 @@ struct EnvArgs {
     int64_t nx, ny, nz;
     int tx_log2;          // columns per tile = 1 << tx_log2
     uint64_t ntiles;
+    const uint32_t* gate; // when set, the pass runs only if *gate != 0 (streaming outward search only)
 };
+
+// Word of the workspace header that the fused y/z pass of the first EDT
+// raises when some voxel's distance lies beyond its search disc (cleared
+// with the status word).
+#define QAI_WIDE_WORD 16
 
 struct InterpArgs {
     const uint32_t* w1;

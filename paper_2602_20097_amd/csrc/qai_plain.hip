@@ -19,6 +19,7 @@
 // the streaming ones by HBM.
 #include "qai_device.h"
 #include "qai_kernels.h"
+#include <algorithm>
 #include <type_traits>
 
 namespace qai {
@@ -1267,6 +1268,8 @@ __global__ __launch_bounds__(64 * WPB) void k_env_swin(EnvArgs a)
     const int64_t stride = (AXIS == 1) ? a.nx : a.nx * a.ny;
     const int64_t nxb = (a.nx + 63) >> 6;
     const uint64_t ngroups = (a.ntiles + WPB - 1) / WPB;
+    if (a.gate && *a.gate == 0u)
+        return; // gated pass not needed (uniform over the grid)
 
     for (uint64_t t = blockIdx.x; t < ngroups; t += gridDim.x) {
         const uint64_t tile = xcd_remap(t, ngroups) * WPB + wv;
@@ -2638,6 +2641,183 @@ static hipError_t launch_swin_t(EnvArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
+// ----------------------------------------------- first EDT, y and z at once
+// After the x pass, the first EDT's y and z passes together give, at each
+// voxel, the minimum over (z', y') of G(z', y') + (z - z')^2 + (y - y')^2 (G:
+// the x-pass distance in row (z', y')), the separable passes keeping among
+// equal values the lowest z', then the lowest y' (Algorithm 1's strict
+// comparisons along each axis): the lexicographically smallest (z', y').
+// B1 is dense and its distances short, so one pass takes that minimum over a
+// disc of offsets directly: a voxel with G = best = b is final once every
+// offset with dz^2 + dy^2 <= b has been compared (any other candidate costs
+// more than b), and offsets are taken in order of dz^2 + dy^2.  A voxel whose
+// best exceeds the disc (radius^2 YZ_R2), or has no site in it, raises *wide;
+// the separable passes then run after it (gated on *wide) and recompute the
+// whole field exactly.
+constexpr int YZ_R = 12, YZ_R2 = YZ_R * YZ_R;
+struct YzTable {
+    uint32_t e[512]; // (dz^2 + dy^2) << 16 | (dz + 128) << 8 | (dy + 128), ascending; padded with all ones
+    int n;           // entries, padding excluded
+};
+constexpr YzTable make_yz_table()
+{
+    YzTable t{};
+    int n = 0;
+    for (int dz = -YZ_R; dz <= YZ_R; ++dz)
+        for (int dy = -YZ_R; dy <= YZ_R; ++dy) {
+            const int d2 = dz * dz + dy * dy;
+            if (d2 == 0 || d2 > YZ_R2)
+                continue;
+            const uint32_t v = ((uint32_t)d2 << 16) | ((uint32_t)(dz + 128) << 8) | (uint32_t)(dy + 128);
+            int k = n++;
+            while (k > 0 && t.e[k - 1] > v) {
+                t.e[k] = t.e[k - 1];
+                --k;
+            }
+            t.e[k] = v;
+        }
+    t.n = n;
+    while (n % 4)
+        t.e[n++] = 0xFFFFFFFFu;
+    return t;
+}
+__constant__ YzTable c_yz = make_yz_table();
+
+// Four consecutive voxels of a row per quad (nx a multiple of 4).  A block
+// takes 1024 quads at a time, four per thread 256 apart (their loads in
+// flight together), writes the quads whose four voxels are sites (distance
+// 0: final, most of the field) and lists the others in LDS; its threads then
+// search the listed quads one each, so only as many waves as the list needs
+// run the search.  Each offset of the disc is one 16-byte load serving a
+// quad's four voxels.  The key of the chosen site's offset,
+// (dz + 128) << 8 | (dy + 128), orders like (z', y').  IDX is the index type
+// (32-bit below 2^32 voxels).
+template <typename IDX>
+__global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide)
+{
+    constexpr int U = 4;
+    __shared__ uint16_t list[256 * U];
+    __shared__ int wsum[4 * U];
+    const IDX nx = (IDX)a.nx, ny = (IDX)a.ny, nz = (IDX)a.nz, plane = nx * ny;
+    const IDX nq = plane * nz / 4;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ntab = c_yz.n;
+    bool unsettled = false;
+    for (IDX q0 = (IDX)blockIdx.x * (256 * U); q0 < nq; q0 += (IDX)gridDim.x * (256 * U)) {
+        uint4 c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const IDX q = min(q0 + (IDX)(u * 256 + tid), nq - 1);
+            c[u] = *reinterpret_cast<const uint4*>(a.win + (int64_t)q * 4);
+        }
+        uint64_t m[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const IDX q = q0 + (IDX)(u * 256 + tid);
+            const bool valid = q < nq;
+            const bool sites = ((c[u].x | c[u].y | c[u].z | c[u].w) >> 2) == 0u;
+            if (valid && sites)
+                *reinterpret_cast<uint4*>(a.w + (int64_t)q * 4) = c[u];
+            m[u] = __ballot(valid && !sites);
+        }
+        // list order: u-major, then wave, then lane
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                wsum[u * 4 + wv] = __popcll(m[u]);
+        }
+        lds_barrier();
+        int total = 0, before[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if (w == wv)
+                    before[u] = total;
+                total += wsum[u * 4 + w];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if ((m[u] >> lane) & 1ull)
+                list[before[u] + __popcll(m[u] & ((1ull << lane) - 1ull))] = (uint16_t)(u * 256 + tid);
+        lds_barrier();
+#pragma unroll 1
+        for (int k = tid; k < total; k += 256) {
+            const IDX i = (q0 + (IDX)list[k]) * 4;
+            const IDX z = i / plane, y = (i - z * plane) / nx;
+            const uint4 cc = *reinterpret_cast<const uint4*>(a.win + (int64_t)i);
+            uint32_t bw[4] = {cc.x, cc.y, cc.z, cc.w};
+            uint32_t bk[4] = {0x8080u, 0x8080u, 0x8080u, 0x8080u};
+            auto limit = [&]() {
+                uint32_t l = 0u;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    l = max(l, bw[q] == QAI_WORD_INF ? 0xFFFFu : (bw[q] >> 2));
+                return l;
+            };
+            uint32_t lim = limit();
+            // batches of four offsets, uniform over the wave
+#pragma unroll 1
+            for (int j = 0; j < ntab; j += 4) {
+                const bool go = lim >= (c_yz.e[j] >> 16);
+                if (__ballot(go) == 0ull)
+                    break;
+                if (go) {
+                    uint4 v[4];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const uint32_t e = c_yz.e[j + b];
+                        const int dz = (int)((e >> 8) & 255u) - 128, dy = (int)(e & 255u) - 128;
+                        const int64_t zc = (int64_t)z + dz, yc = (int64_t)y + dy;
+                        const bool ok = e != 0xFFFFFFFFu && zc >= 0 && zc < (int64_t)nz && yc >= 0 && yc < (int64_t)ny;
+                        // a valid address either way; the value of an offset outside the field is dropped
+                        const int64_t o = ok ? (int64_t)i + (int64_t)dz * (int64_t)plane + (int64_t)dy * (int64_t)nx
+                                             : (int64_t)i;
+                        const uint4 l = *reinterpret_cast<const uint4*>(a.win + o);
+                        v[b].x = ok ? l.x : QAI_WORD_INF;
+                        v[b].y = ok ? l.y : QAI_WORD_INF;
+                        v[b].z = ok ? l.z : QAI_WORD_INF;
+                        v[b].w = ok ? l.w : QAI_WORD_INF;
+                    }
+                    // An absent site (all ones) reads as distance 2^30 - 1, above
+                    // every real distance plus d2 (< 3 * 16383^2 + 144), so it
+                    // never wins, and any real candidate beats an absent best.
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const uint32_t e = c_yz.e[j + b];
+                        const uint32_t d2 = e >> 16, key = e & 0xFFFFu;
+                        const uint32_t cw[4] = {v[b].x, v[b].y, v[b].z, v[b].w};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const uint32_t t = (cw[q] >> 2) + d2, bd = bw[q] >> 2;
+                            const bool better = (t < bd) | ((t == bd) & (key < bk[q]));
+                            bw[q] = better ? ((t << 2) | (cw[q] & 3u)) : bw[q];
+                            bk[q] = better ? key : bk[q];
+                        }
+                    }
+                    lim = limit();
+                }
+            }
+            unsettled |= lim > (uint32_t)YZ_R2;
+            *reinterpret_cast<uint4*>(a.w + (int64_t)i) = make_uint4(bw[0], bw[1], bw[2], bw[3]);
+        }
+        lds_barrier(); // the list and wsum are rewritten next round
+    }
+    if (__ballot(unsettled) != 0ull && lane == 0)
+        atomicOr(wide, 1u);
+}
+
+static hipError_t launch_edt1_yz(const EnvArgs& a, uint32_t* wide, hipStream_t s)
+{
+    const int64_t n = a.nx * a.ny * a.nz, nq = n / 4;
+    const uint32_t grid = grid_cap((uint64_t)((nq + 1023) / 1024), 1u << 20);
+    if (n < ((int64_t)1 << 32))
+        hipLaunchKernelGGL(k_edt1_yz<uint32_t>, dim3(grid), dim3(256), 0, s, a, wide);
+    else
+        hipLaunchKernelGGL(k_edt1_yz<int64_t>, dim3(grid), dim3(256), 0, s, a, wide);
+    return hipGetLastError();
+}
+
 hipError_t launch_env(int axis, EnvArgs a, const Tuning& t, hipStream_t s)
 {
     const int64_t n = axis == 1 ? a.ny : a.nz;
@@ -2742,7 +2922,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
     }
     uint32_t* buf[3] = {p.bufA, p.bufB, p.bufC};
     prof_begin("clear", s);
-    QAI_TRY(launch_clear(p.status, 1, s));
+    QAI_TRY(launch_clear(p.status, QAI_WIDE_WORD + 1, s));
     prof_end(s);
 
     SeedArgs sa = {};
@@ -2760,8 +2940,12 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
     sa.td1 = p.taps.d1sq;
     sa.tb2 = p.taps.b2;
 
-    // step A + x pass of step B
-    int cur = 0;
+    // step A + x pass of step B; a 3-D field with both passes of the first
+    // EDT on automatic takes them as one search over (y, z) (k_edt1_yz), the
+    // separable passes gated behind it; the final words land in buffer 0
+    // either way
+    const bool yz = p.nz > 1 && p.ny > 1 && p.nx % 4 == 0 && t_in.edt1_algo[1] < 0 && t_in.edt1_algo[2] < 0;
+    int cur = yz ? 1 : 0;
     sa.wout = buf[cur];
     prof_begin("seed1_xscan", s);
     QAI_TRY(launch_seed(0, sa, s, t.seed_ty, t.seed_tz));
@@ -2776,7 +2960,28 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         t1.stream_cap[i] = t.edt1_cap[i];
         t1.env_algo[i] = t.edt1_algo[i];
     }
-    if (p.ny > 1) {
+    if (yz) {
+        uint32_t* wide = p.status + QAI_WIDE_WORD;
+        ea.win = buf[1];
+        ea.w = buf[0];
+        prof_begin("edt1_yz", s);
+        QAI_TRY(launch_edt1_yz(ea, wide, s));
+        prof_end(s);
+        // the fallback: the streaming outward search, the kernel that reads the gate
+        Tuning tf = t1;
+        tf.env_algo[1] = tf.env_algo[2] = 4;
+        ea.gate = wide;
+        prof_begin("edt1_fallback", s);
+        ea.win = buf[1];
+        ea.w = buf[2];
+        QAI_TRY(launch_env(1, ea, tf, s));
+        ea.win = buf[2];
+        ea.w = buf[0];
+        QAI_TRY(launch_env(2, ea, tf, s));
+        prof_end(s);
+        ea.gate = nullptr;
+        cur = 0;
+    } else if (p.ny > 1) {
         ea.win = buf[cur];
         ea.w = buf[cur ^ 1];
         prof_begin("edt1_y", s);
@@ -2784,7 +2989,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         prof_end(s);
         cur ^= 1;
     }
-    if (p.nz > 1) {
+    if (p.nz > 1 && !yz) {
         ea.win = buf[cur];
         ea.w = buf[cur ^ 1];
         prof_begin("edt1_z", s);

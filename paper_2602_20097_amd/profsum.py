@@ -28,6 +28,7 @@ STAGES = [
     (r"k_seed_(lane|seg|slab|xscan|lines)<0", "seed1_xscan"),
     (r"k_seed_(lane|seg|slab|xscan|lines)<1", "seed2_xscan"),
     (r"k_interp_(own|far)", "edt2_z_interp"),
+    (r"k_edt1_yz", "edt1_yz"),
     (r"k_interp\b", "interp"),
     (r"k_copy", "copy_probe"),
     (r"k_clear", "clear"),
@@ -52,12 +53,15 @@ def _one(pattern):
     return files[-1]
 
 
-def stage_of(name, order):
+def stage_of(name, order, fused=False):
     """Envelope passes are told apart by their order within a step: the first
-    EDT's y and z passes come before the second seed pass."""
+    EDT's y and z passes come before the second seed pass; after the fused
+    y/z search of the first EDT they are its gated fallback."""
     for pat, st in STAGES:
         if re.search(pat, name):
             return st
+    if re.search(r"k_env_\w+<[12]", name) and order == 0 and fused:
+        return "edt1_fallback"
     if re.search(r"k_env_\w+<1", name):
         return "edt1_y" if order == 0 else "edt2_y"
     if re.search(r"k_env_\w+<2", name):
@@ -78,16 +82,18 @@ def _per_step(events):
     """events: (name, value) in dispatch order.  A step starts at its first
     seed kernel; the values of a stage's kernels are summed within a step and
     averaged over steps (the copy probe, outside the steps, per launch)."""
-    steps, cur, seen_seed2 = [], None, False
+    steps, cur, seen_seed2, fused = [], None, False, False
     copy = []
     for name, val in events:
         if re.search(SEED1, name):
             cur = {}
             steps.append(cur)
-            seen_seed2 = False
+            seen_seed2 = fused = False
         if re.search(SEED2, name):
             seen_seed2 = True
-        st = stage_of(name, 1 if seen_seed2 else 0)
+        if re.search(r"k_edt1_yz", name):
+            fused = True
+        st = stage_of(name, 1 if seen_seed2 else 0, fused)
         if st == "copy_probe":
             copy.append(val)
         elif st and cur is not None:

@@ -225,6 +225,21 @@ def test_blocked_handoff_to_the_needed_voxel_search():
     assert qai.get_tuning() == base
 
 
+def test_first_edt_beyond_the_search_disc():
+    """The first EDT's y and z passes run as one search over a disc of radius
+    12 around each voxel; a voxel farther from B1 raises a flag and the
+    separable passes behind the search recompute the field.  A 30-voxel
+    plateau of one index puts its centre 15 voxels from B1; a constant field
+    has no B1 at all."""
+    x32, xq, q, eb = synth.quantize(synth.grf((40, 40, 40), 3.0, 77), 1e-2)
+    xq = xq.copy()
+    xq[5:35, 5:35, 5:35] = xq[20, 20, 20]
+    r = oracle.qai(xq, eb)
+    assert r["d1sq"].max() > 144
+    assert_parity(xq, eb, label="plateau")
+    assert_parity(np.full((6, 8, 12), 3.0, np.float32), 0.5, label="constant")
+
+
 def test_every_pass_algorithm_gives_the_same_transform():
     """Each per-pass algorithm choice (qai_tuning) computes the same exact EDTs."""
     import paper_2602_20097_amd as qai
