@@ -27,6 +27,8 @@ struct SeedArgs {
     uint8_t* tb2;
     uint64_t ngroups;     // line groups (one line per wave)
     int waves;            // waves per workgroup
+    unsigned long long* b1count; // mode 0, k_seed_lane only (nullable): an estimate of the B1 voxels
+                                 // (a 1-in-V sample, scaled) is added here
 };
 
 // One lower-envelope pass along y (axis 1) or z (axis 2) over packed words,
@@ -40,10 +42,13 @@ struct EnvArgs {
     const uint32_t* gate; // when set, the pass runs only if *gate != 0 (streaming outward search only)
 };
 
-// Word of the workspace header that the fused y/z pass of the first EDT
-// raises when some voxel's distance lies beyond its search disc (cleared
-// with the status word).
+// Words of the workspace header for the fused y/z pass of the first EDT,
+// cleared with the status word: QAI_WIDE_WORD is raised when some voxel's
+// distance lies beyond the search disc (or the pass stands down), and the
+// 64-bit estimate of the B1 voxels from the seed pass sits at QAI_B1_WORD.
 #define QAI_WIDE_WORD 16
+#define QAI_B1_WORD 18
+#define QAI_HEADER_WORDS 20
 
 struct InterpArgs {
     const uint32_t* w1;

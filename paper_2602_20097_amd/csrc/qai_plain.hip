@@ -571,6 +571,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
     constexpr int W = V * 64;
     constexpr int R = WPB + 2;
     __shared__ uint32_t rows[2][R * W];
+    __shared__ unsigned long long b1sum;
     const SeedArgs& a = A.s;
     const int nx = (int)a.nx;
     const int64_t ny = a.ny, nz = a.nz;
@@ -586,6 +587,12 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
     const uint64_t upper = (lane == 63) ? 0ull : (~0ull << (lane + 1));  // strictly above
     const uint64_t nblocks = (uint64_t)(A.nby * A.nbz);
     bool bad = false;
+    uint32_t nb1 = 0u; // mode 0: B1 among the lanes' first voxels, a 1-in-V sample (wave-uniform)
+    if (MODE == 0 && a.b1count) {
+        if (threadIdx.x == 0)
+            b1sum = 0ull;
+        lds_barrier();
+    }
 
     // Site value of voxel x with payload code: ((x + 4096) << 2) | code, so
     // values order like positions.  "No site" to the left is 0, to the right
@@ -728,6 +735,8 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                         }
                     }
                     sv[j] = ((uint32_t)(x + 4096) << 2) | code;
+                    if (MODE == 0 && j == 0)
+                        nb1 += (uint32_t)__popcll(__ballot(st[0]));
                 }
                 // nearest site at or before / at or after each voxel among the
                 // lane's own, then the carries: the last site of the nearest lane
@@ -808,6 +817,13 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
     }
     if (MODE == 0 && __ballot(bad) && (threadIdx.x & 63) == 0)
         atomicOr(a.status, QAI_STATUS_QRANGE);
+    if (MODE == 0 && a.b1count) {
+        if ((threadIdx.x & 63) == 0)
+            atomicAdd(&b1sum, (unsigned long long)nb1 * V);
+        lds_barrier();
+        if (threadIdx.x == 0)
+            atomicAdd(a.b1count, b1sum);
+    }
 }
 
 // ---------------------------------------------------------- interpolation
@@ -2653,7 +2669,8 @@ static hipError_t launch_swin_t(EnvArgs a, hipStream_t s)
 // more than b), and offsets are taken in order of dz^2 + dy^2.  A voxel whose
 // best exceeds the disc (radius^2 YZ_R2), or has no site in it, raises *wide;
 // the separable passes then run after it (gated on *wide) and recompute the
-// whole field exactly.
+// whole field exactly, and blocks that start after the flag is up stop at
+// once (sparse B1: the pass costs little more than the separable passes).
 constexpr int YZ_R = 12, YZ_R2 = YZ_R * YZ_R;
 struct YzTable {
     uint32_t e[512]; // (dz^2 + dy^2) << 16 | (dz + 128) << 8 | (dy + 128), ascending; padded with all ones
@@ -2693,11 +2710,12 @@ __constant__ YzTable c_yz = make_yz_table();
 // (dz + 128) << 8 | (dy + 128), orders like (z', y').  IDX is the index type
 // (32-bit below 2^32 voxels).
 template <typename IDX>
-__global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide)
+__global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide, const unsigned long long* b1count)
 {
     constexpr int U = 4;
     __shared__ uint16_t list[256 * U];
     __shared__ int wsum[4 * U];
+    __shared__ uint32_t stop;
     const IDX nx = (IDX)a.nx, ny = (IDX)a.ny, nz = (IDX)a.nz, plane = nx * ny;
     const IDX nq = plane * nz / 4;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -2709,6 +2727,18 @@ __global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide)
         for (int u = 0; u < U; ++u) {
             const IDX q = min(q0 + (IDX)(u * 256 + tid), nq - 1);
             c[u] = *reinterpret_cast<const uint4*>(a.win + (int64_t)q * 4);
+        }
+        // once some block has raised *wide the separable passes recompute the
+        // whole field: the rest of this pass is moot (what a block wrote before
+        // it stops is overwritten).  With B1 below 90% of the field the searches
+        // would be long and often end beyond the disc: the pass stands down at
+        // once (block 0 raises the flag).  Read with the quads, acted on at the
+        // list barrier.
+        if (tid == 0) {
+            const bool sparse = *b1count * 10ull < (unsigned long long)(plane * nz) * 9ull;
+            if (sparse && blockIdx.x == 0 && q0 == 0)
+                atomicOr(wide, 1u);
+            stop = sparse || __hip_atomic_load(wide, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         }
         uint64_t m[U];
 #pragma unroll
@@ -2727,6 +2757,8 @@ __global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide)
                 wsum[u * 4 + wv] = __popcll(m[u]);
         }
         lds_barrier();
+        if (stop)
+            break;
         int total = 0, before[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -2807,14 +2839,14 @@ __global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide)
         atomicOr(wide, 1u);
 }
 
-static hipError_t launch_edt1_yz(const EnvArgs& a, uint32_t* wide, hipStream_t s)
+static hipError_t launch_edt1_yz(const EnvArgs& a, uint32_t* wide, const unsigned long long* b1count, hipStream_t s)
 {
     const int64_t n = a.nx * a.ny * a.nz, nq = n / 4;
     const uint32_t grid = grid_cap((uint64_t)((nq + 1023) / 1024), 1u << 20);
     if (n < ((int64_t)1 << 32))
-        hipLaunchKernelGGL(k_edt1_yz<uint32_t>, dim3(grid), dim3(256), 0, s, a, wide);
+        hipLaunchKernelGGL(k_edt1_yz<uint32_t>, dim3(grid), dim3(256), 0, s, a, wide, b1count);
     else
-        hipLaunchKernelGGL(k_edt1_yz<int64_t>, dim3(grid), dim3(256), 0, s, a, wide);
+        hipLaunchKernelGGL(k_edt1_yz<int64_t>, dim3(grid), dim3(256), 0, s, a, wide, b1count);
     return hipGetLastError();
 }
 
@@ -2922,7 +2954,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
     }
     uint32_t* buf[3] = {p.bufA, p.bufB, p.bufC};
     prof_begin("clear", s);
-    QAI_TRY(launch_clear(p.status, QAI_WIDE_WORD + 1, s));
+    QAI_TRY(launch_clear(p.status, QAI_HEADER_WORDS, s));
     prof_end(s);
 
     SeedArgs sa = {};
@@ -2944,7 +2976,10 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
     // EDT on automatic takes them as one search over (y, z) (k_edt1_yz), the
     // separable passes gated behind it; the final words land in buffer 0
     // either way
-    const bool yz = p.nz > 1 && p.ny > 1 && p.nx % 4 == 0 && t_in.edt1_algo[1] < 0 && t_in.edt1_algo[2] < 0;
+    const bool yz = p.nz > 1 && p.ny > 1 && p.nx % 4 == 0 && p.nx <= 512 && t.seed_ty == 0 &&
+                    t_in.edt1_algo[1] < 0 && t_in.edt1_algo[2] < 0; // seed pass: k_seed_lane (counts B1)
+    unsigned long long* const b1count = (unsigned long long*)(p.status + QAI_B1_WORD);
+    sa.b1count = yz ? b1count : nullptr;
     int cur = yz ? 1 : 0;
     sa.wout = buf[cur];
     prof_begin("seed1_xscan", s);
@@ -2965,7 +3000,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         ea.win = buf[1];
         ea.w = buf[0];
         prof_begin("edt1_yz", s);
-        QAI_TRY(launch_edt1_yz(ea, wide, s));
+        QAI_TRY(launch_edt1_yz(ea, wide, b1count, s));
         prof_end(s);
         // the fallback: the streaming outward search, the kernel that reads the gate
         Tuning tf = t1;
@@ -3005,6 +3040,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
     sa.w1 = buf[w1];
     sa.wout = buf[c2];
     prof_begin("seed2_xscan", s);
+    sa.b1count = nullptr;
     QAI_TRY(launch_seed(1, sa, s, t.seed_ty, t.seed_tz));
     prof_end(s);
 

@@ -227,15 +227,23 @@ def test_blocked_handoff_to_the_needed_voxel_search():
 
 def test_first_edt_beyond_the_search_disc():
     """The first EDT's y and z passes run as one search over a disc of radius
-    12 around each voxel; a voxel farther from B1 raises a flag and the
-    separable passes behind the search recompute the field.  A 30-voxel
-    plateau of one index puts its centre 15 voxels from B1; a constant field
-    has no B1 at all."""
+    12 around each voxel when B1 covers at least 90% of the field; a voxel
+    farther from B1 raises a flag and the separable passes behind the search
+    recompute the field, and with sparser B1 the search stands down for
+    them.  Dense B1 (random indices) around a 28-voxel plateau puts the
+    plateau's centre 13 voxels from B1; a 30-voxel plateau in a smooth field
+    makes B1 sparse; a constant field has no B1 at all."""
+    rng = np.random.default_rng(31)
+    xq = rng.integers(-3, 4, size=(96, 96, 96)).astype(np.float32)
+    xq[34:62, 34:62, 34:62] = 7.0
+    r = oracle.qai(xq, 0.5)
+    assert r["b1"].mean() >= 0.9 and r["d1sq"].max() > 144
+    assert_parity(xq, 0.5, label="dense with a hole")
     x32, xq, q, eb = synth.quantize(synth.grf((40, 40, 40), 3.0, 77), 1e-2)
     xq = xq.copy()
     xq[5:35, 5:35, 5:35] = xq[20, 20, 20]
     r = oracle.qai(xq, eb)
-    assert r["d1sq"].max() > 144
+    assert r["b1"].mean() < 0.9 and r["d1sq"].max() > 144
     assert_parity(xq, eb, label="plateau")
     assert_parity(np.full((6, 8, 12), 3.0, np.float32), 0.5, label="constant")
 
