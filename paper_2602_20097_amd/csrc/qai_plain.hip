@@ -1161,7 +1161,8 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords, Fa
             const uint32_t d2 = zsearch<BUF>(g, jg, gplane, z, (int)a.nz);
             a.out[i] = interp_at(a, i, w, xv, d2);
         }
-        lds_barrier();
+        if (w0 + L < total) // after the last window, threads without searches leave at once
+            lds_barrier();
     }
 }
 
@@ -2833,7 +2834,10 @@ __global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide, cons
             unsettled |= lim > (uint32_t)YZ_R2;
             *reinterpret_cast<uint4*>(a.w + (int64_t)i) = make_uint4(bw[0], bw[1], bw[2], bw[3]);
         }
-        lds_barrier(); // the list and wsum are rewritten next round
+        // the list and wsum are rewritten next round; after the last round
+        // waves without searches leave at once (their slots go to other blocks)
+        if (q0 + (IDX)gridDim.x * (256 * U) < nq)
+            lds_barrier();
     }
     if (__ballot(unsettled) != 0ull && lane == 0)
         atomicOr(wide, 1u);
