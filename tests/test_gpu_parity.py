@@ -246,6 +246,14 @@ def test_first_edt_beyond_the_search_disc():
     assert r["b1"].mean() < 0.9 and r["d1sq"].max() > 144
     assert_parity(xq, eb, label="plateau")
     assert_parity(np.full((6, 8, 12), 3.0, np.float32), 0.5, label="constant")
+    # 2-D fields take the separable passes (here a plateau farther than 12 from B1
+    # and dense random indices)
+    x2 = rng.integers(-3, 4, size=(1, 64, 72)).astype(np.float32)
+    x2[:, 17:47, 20:50] = 7.0
+    r = oracle.qai(x2, 0.5)
+    assert r["d1sq"].max() > 144
+    assert_parity(x2, 0.5, label="2-D plateau")
+    assert_parity(rng.integers(-3, 4, size=(1, 50, 96)).astype(np.float32), 0.5, label="2-D dense")
 
 
 def test_every_pass_algorithm_gives_the_same_transform():
