@@ -2115,8 +2115,12 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
     uint32_t* const sl = stage + (BLK ? (wv * 64 + lane) * 4 : 0);
 #define SLOT(k) (((k) & (C - 1)) * 64)
 
+    // Tiles in dispatch order, not xcd_remap'd: a tile shares no cache line with
+    // its neighbours, and the envelope's work follows the density of sites,
+    // which changes from plane to plane: consecutive planes on different XCDs
+    // spread the heavy ones.
     for (uint64_t t = blockIdx.x; t < ngroups; t += gridDim.x) {
-        const uint64_t tile = xcd_remap(t, ngroups) * WPB + wv;
+        const uint64_t tile = t * WPB + wv;
         if (tile >= a.ntiles)
             continue;
         const int64_t xb = (int64_t)(tile % (uint64_t)nxb), o = (int64_t)(tile / (uint64_t)nxb);
