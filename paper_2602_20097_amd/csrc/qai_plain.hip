@@ -1288,8 +1288,10 @@ __global__ __launch_bounds__(64 * WPB) void k_env_swin(EnvArgs a)
     if (a.gate && *a.gate == 0u)
         return; // gated pass not needed (uniform over the grid)
 
+    // tiles in dispatch order (as in k_env_lane2: no shared lines, work that
+    // follows the density of sites plane by plane)
     for (uint64_t t = blockIdx.x; t < ngroups; t += gridDim.x) {
-        const uint64_t tile = xcd_remap(t, ngroups) * WPB + wv;
+        const uint64_t tile = t * WPB + wv;
         if (tile >= a.ntiles)
             continue;
         const int64_t xb = (int64_t)(tile % (uint64_t)nxb), o = (int64_t)(tile / (uint64_t)nxb);
