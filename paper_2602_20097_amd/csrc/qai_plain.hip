@@ -1069,16 +1069,19 @@ __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
 // voxels in the same (y, x) column and nearby planes read the same y-pass
 // lines, so where a plane holds whole waves (nx ny a multiple of 256) a block
 // takes 8 consecutive waves (whole rows) of 8 consecutive planes, and the
-// blocks run on each XCD (block b on XCD b % 8) walk a column group through a
-// quarter of the planes in order: the lines they read stay in that XCD's L2.
-// Column groups are dealt to the XCDs from both y faces inward, a quarter of
-// the planes per XCD: the face rows, where B2 never lies and every needed
-// voxel is flagged, are spread over all eight and taken first.  Otherwise a
-// block takes 64 waves spaced gridDim.x apart.
+// blocks on each XCD (block b runs on XCD b % 8) walk a column group through
+// a chunk of 32 planes in order: the lines they read stay in that XCD's L2.
+// Chunk c of column group j goes to XCD (j + c) % 8, so every XCD takes
+// planes from the whole depth (the density of far voxels follows that of B2,
+// plane by plane); column groups are taken from both y faces inward, where B2
+// never lies and every needed voxel is flagged, so those heavy rows come
+// first.  Otherwise a block takes 64 waves spaced gridDim.x apart.
 struct FarMap {
-    int64_t wpp;          // waves per plane (0: the spaced mapping)
-    int64_t pb, zb, zbq;  // 8-wave groups per plane, 8-plane groups, 8-plane groups per quarter
+    int64_t wpp;      // waves per plane (0: the spaced mapping)
+    int64_t pb, zb;   // 8-wave groups per plane, 8-plane groups
+    int64_t ncx;      // chunks of FAR_ZC 8-plane groups per XCD and column group
 };
+constexpr int FAR_ZC = 4;
 
 __device__ __forceinline__ int64_t far_wave(const FarMap& f, int64_t nz, int64_t nwaves, int lw)
 {
@@ -1088,8 +1091,9 @@ __device__ __forceinline__ int64_t far_wave(const FarMap& f, int64_t nz, int64_t
     }
     const int k = blockIdx.x & 7;
     const int64_t u = blockIdx.x >> 3;
-    const int64_t j = 2 * (u / f.zbq) + (k >> 2);
-    const int64_t zb = (k & 3) * f.zbq + u % f.zbq;
+    const int64_t unit = u / FAR_ZC, j = unit / f.ncx;
+    const int64_t zc = ((k - j) % 8 + 8) % 8 + 8 * (unit % f.ncx);
+    const int64_t zb = zc * FAR_ZC + u % FAR_ZC;
     if (j >= f.pb || zb >= f.zb)
         return -1;
     const int64_t cg = (j & 1) ? f.pb - 1 - (j >> 1) : (j >> 1);
@@ -1181,8 +1185,8 @@ static hipError_t launch_interp_search_t(const ZsArgs& a, int64_t blocks, hipStr
         fm.wpp = plane / 256;
         fm.pb = (fm.wpp + 7) / 8;
         fm.zb = (a.nz + 7) / 8;
-        fm.zbq = (fm.zb + 3) / 4;
-        grid = 8 * ((fm.pb + 1) / 2) * fm.zbq;
+        fm.ncx = ((fm.zb + FAR_ZC - 1) / FAR_ZC + 7) / 8;
+        grid = 8 * fm.pb * fm.ncx * FAR_ZC;
     }
     hipLaunchKernelGGL((k_interp_far<BUF, BLK>), dim3((unsigned)grid), dim3(256), 0, s, a, nwords, fm);
     return hipGetLastError();
