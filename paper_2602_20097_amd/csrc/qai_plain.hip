@@ -1070,7 +1070,7 @@ __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
 // lines, so where a plane holds whole waves (nx ny a multiple of 256) a block
 // takes 8 consecutive waves (whole rows) of 8 consecutive planes, and the
 // blocks on each XCD (block b runs on XCD b % 8) walk a column group through
-// a chunk of 32 planes in order: the lines they read stay in that XCD's L2.
+// a chunk of 64 planes in order: the lines they read stay in that XCD's L2.
 // Chunk c of column group j goes to XCD (j + c) % 8, so every XCD takes
 // planes from the whole depth (the density of far voxels follows that of B2,
 // plane by plane); column groups are taken from both y faces inward, where B2
@@ -1081,7 +1081,7 @@ struct FarMap {
     int64_t pb, zb;   // 8-wave groups per plane, 8-plane groups
     int64_t ncx;      // chunks of FAR_ZC 8-plane groups per XCD and column group
 };
-constexpr int FAR_ZC = 4;
+constexpr int FAR_ZC = 8;
 
 __device__ __forceinline__ int64_t far_wave(const FarMap& f, int64_t nz, int64_t nwaves, int lw)
 {
