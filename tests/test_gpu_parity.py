@@ -80,8 +80,10 @@ def test_hand_examples():
     assert_parity(np.broadcast_to(k // 8, (3, 3, 32)).astype(np.float32).copy(), 0.5, label="extrusion")
 
 
+# (75, 48, 64): planes of whole waves of the streaming kernel (12 per plane) with a
+# partial group of 8 and a partial chunk of planes in the needed-voxel search
 SHAPES = [(5, 70, 130), (3, 65, 200), (1, 1, 1000), (1, 300, 1), (17, 1, 129), (9, 33, 1), (2, 2, 2),
-          (1, 1, 1), (4, 129, 63), (70, 5, 66), (1, 257, 300), (33, 33, 33)]
+          (1, 1, 1), (4, 129, 63), (70, 5, 66), (1, 257, 300), (33, 33, 33), (75, 48, 64)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
