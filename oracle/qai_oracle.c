@@ -141,60 +141,77 @@ void orc_boundary_sign(const int32_t* q, int64_t nz, int64_t ny, int64_t nx, uin
         }
         if (!found)
             continue;
-        B[i] = 1;                                   /* mark as quantization boundary */
-        S[i] = (int8_t)(first_diff > 0 ? 1 : -1);   /* sgn(q_neighbor - q) */
-        for (int a = 0; a < 3; ++a) {               /* central-difference gradient */
+        B[i] = 1;                                   /* in B1 */
+        S[i] = (int8_t)(first_diff > 0 ? 1 : -1);   /* sign of (first differing neighbour - q) */
+        for (int a = 0; a < 3; ++a) {               /* half the index jump across the voxel, per axis */
             if (g.n[a] == 1)
                 continue;
             double grad = fabs((double)((int64_t)q[i + g.stride[a]] - (int64_t)q[i - g.stride[a]])) / 2.0;
             if (grad >= 1.0)
-                S[i] = 0;                           /* fast-varying region: discard sign */
+                S[i] = 0;                           /* steep: the error sign is not predictable */
         }
     }
 }
 
-/* RemoveEDT(g_{l-1}, g_l, f_i, h_{l-1}, h_l): true when
- * c g_l - b g_{l-1} - a f_i - a b c > 0, a = h_l - h_{l-1}, b = i - h_l,
- * c = i - h_{l-1} (Section III-B). */
-static int remove_edt(int64_t g_lm1, int64_t g_l, int64_t f_i, int64_t h_lm1, int64_t h_l, int64_t i)
+/* The squared distance transform along one line is Eq. 2 restricted to the
+ * line: D(i) = min over sites j of f(j) + (i - j)^2, where the sites are the
+ * entries with f(j) finite.  Seen as functions of i, the terms are parabolas
+ * P_j of one common curvature, so each parabola is the minimum on at most one
+ * interval, and those intervals come in the order of the sites.  Algorithm 1
+ * (Section III-B) keeps the parabolas that are the minimum somewhere, in site
+ * order, and then reads the minimum off that list row by row.
+ *
+ * Crossing points: P_v (v > u) drops below P_u for i beyond
+ *   t(u, v) = (f(v) - f(u) + v^2 - u^2) / (2 (v - u)).
+ * With u < v < w, P_v is the minimum nowhere between P_u and P_w when it only
+ * drops below P_u after P_w has already dropped below it: t(u, v) > t(v, w).
+ * Multiplied by 2 (v - u)(w - v) > 0 this is an integer comparison; it is the
+ * same predicate as the paper's RemoveEDT (expand and collect the terms), and
+ * like it, it keeps P_v when the two crossing points coincide. */
+static int parabola_hidden(int64_t fu, int64_t u, int64_t fv, int64_t v, int64_t fw, int64_t w)
 {
-    int64_t a = h_l - h_lm1, b = i - h_l, c = i - h_lm1;
-    return c * g_l - b * g_lm1 - a * f_i - a * b * c > 0;
+    const int64_t a = v - u, b = w - v;
+    return b * (fv - fu + v * v - u * u) > a * (fw - fv + w * w - v * v);
 }
 
-/* Algorithm 1, VoronoiEDT, on one line: D[base + i*stride], i = 0..n-1.
- * Feature indices F (nullable) travel with their sites.  stack_* hold n
- * entries. */
+/* Algorithm 1 on one line: D[base + i*stride], i = 0..n-1 (ORC_INF = not a
+ * site).  Feature indices F (nullable) travel with their sites.  env_* are
+ * scratch arrays of n entries holding the kept parabolas: value, position and
+ * feature. */
 static void voronoi_edt(int64_t* D, int64_t* F, int64_t base, int64_t stride, int64_t n,
-                        int64_t* stack_g, int64_t* stack_h, int64_t* stack_f)
+                        int64_t* env_f, int64_t* env_pos, int64_t* env_feat)
 {
-    int64_t l = 0; /* number of entries; the paper's g_l is stack_g[l-1] */
-    for (int64_t i = 0; i < n; ++i) {               /* construct partial Voronoi diagrams */
-        int64_t f_i = D[base + i * stride];
-        if (f_i == ORC_INF)
-            continue;
-        if (l >= 2) {
-            while (l >= 2 && remove_edt(stack_g[l - 2], stack_g[l - 1], f_i, stack_h[l - 2], stack_h[l - 1], i))
-                l -= 1;
-        }
-        stack_g[l] = f_i;
-        stack_h[l] = i;
-        if (F)
-            stack_f[l] = F[base + i * stride];
-        l += 1;
-    }
-    int64_t n_s = l;
-    if (n_s == 0)
-        return;
-    l = 0;                                          /* query the Voronoi diagram */
+    int64_t kept = 0;
     for (int64_t i = 0; i < n; ++i) {
-        while (l < n_s - 1 &&
-               stack_g[l] + (stack_h[l] - i) * (stack_h[l] - i) >
-                   stack_g[l + 1] + (stack_h[l + 1] - i) * (stack_h[l + 1] - i))
-            l += 1;
-        D[base + i * stride] = stack_g[l] + (stack_h[l] - i) * (stack_h[l] - i);
+        const int64_t fi = D[base + i * stride];
+        if (fi == ORC_INF)
+            continue;
+        /* retire parabolas the new one hides behind their predecessors */
+        while (kept >= 2 && parabola_hidden(env_f[kept - 2], env_pos[kept - 2], env_f[kept - 1], env_pos[kept - 1],
+                                            fi, i))
+            --kept;
+        env_f[kept] = fi;
+        env_pos[kept] = i;
         if (F)
-            F[base + i * stride] = stack_f[l];
+            env_feat[kept] = F[base + i * stride];
+        ++kept;
+    }
+    if (kept == 0)
+        return; /* no site on the line: every entry stays ORC_INF */
+    /* the minimum at row i comes from the current parabola; move on while the
+     * next one is strictly lower there (a tie keeps the lower position) */
+    int64_t cur = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        while (cur + 1 < kept) {
+            const int64_t here = env_f[cur] + (i - env_pos[cur]) * (i - env_pos[cur]);
+            const int64_t next = env_f[cur + 1] + (i - env_pos[cur + 1]) * (i - env_pos[cur + 1]);
+            if (!(next < here))
+                break;
+            ++cur;
+        }
+        D[base + i * stride] = env_f[cur] + (i - env_pos[cur]) * (i - env_pos[cur]);
+        if (F)
+            F[base + i * stride] = env_feat[cur];
     }
 }
 
@@ -317,7 +334,7 @@ void orc_interp(const float* xq, const int64_t* D1, const int64_t* D2, const int
     for (int64_t i = 0; i < n; ++i) {
         double w = idw_weight(D1[i], D2[i], (double)power);
         double C = w * (double)S[i] * e;
-        out[i] = (double)xq[i] + C;  /* compensation added to decompressed data */
+        out[i] = (double)xq[i] + C;  /* D'' = D' + C */
         if (w_out)
             w_out[i] = w;
     }
