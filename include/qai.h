@@ -103,9 +103,13 @@ size_t qai_workspace_bytes(const int64_t dims[3]);
 /* qai_mitigate_ex -- as qai_mitigate with explicit parameters (NULL = the
  * defaults), a caller-owned device workspace ws of ws_bytes >=
  * qai_workspace_bytes(dims) (any alignment of 256 bytes or more), and optional
- * taps (NULL = none).  Afterwards the workspace holds the final distance
- * words of both EDTs, which qai_backward consumes; keep it untouched until
- * then. */
+ * taps (NULL = none).  Afterwards the workspace holds the final distance word
+ * of the first EDT at every voxel, and the final word of the second EDT at
+ * every voxel whose weight depends on it (S != 0 and not on B1), which is all
+ * qai_backward reads; keep the workspace untouched until then.  On a 3-D field
+ * without taps, with default pass choices and 16-byte aligned field and out,
+ * the second EDT's last pass runs only at those voxels, so its words elsewhere
+ * are left unspecified; every other call writes them at every voxel. */
 int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const qai_params* params,
                     void* ws, size_t ws_bytes, float* out, const qai_taps* taps, void* stream);
 
@@ -203,6 +207,10 @@ typedef struct qai_tuning {
                               line-per-wave variant (neighbour lines read through the caches) */
     int32_t seed_planes;   /* z-planes marched per workgroup of the seed passes (>= 1) */
     int32_t window_threads; /* threads per workgroup of the windowed variant (64..1024) */
+    int32_t force_wide;    /* 0 (the default): each kernel picks 32-bit buffer offsets and 32-bit
+                              arithmetic where the field's size allows them; 1: take the 64-bit
+                              index and 64-bit arithmetic variants wherever a kernel has one (same
+                              results; lets small fields exercise the paths large ones take) */
 } qai_tuning;
 
 /* Copy the current setting into *t. */

@@ -250,7 +250,7 @@ def copy_probe(src, dst, stream=None):
 
 
 TUNING_FIELDS = ("edt1_algo", "edt2_algo", "edt1_ring", "edt2_ring", "tile_log2", "seed_rows", "seed_planes",
-                 "window_threads")
+                 "window_threads", "force_wide")
 
 
 def get_tuning():

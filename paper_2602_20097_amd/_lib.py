@@ -39,7 +39,7 @@ class Taps(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("edt1_algo", ctypes.c_int32 * 2), ("edt2_algo", ctypes.c_int32 * 2), ("edt1_ring", ctypes.c_int32),
                 ("edt2_ring", ctypes.c_int32), ("tile_log2", ctypes.c_int32 * 2), ("seed_rows", ctypes.c_int32),
-                ("seed_planes", ctypes.c_int32), ("window_threads", ctypes.c_int32)]
+                ("seed_planes", ctypes.c_int32), ("window_threads", ctypes.c_int32), ("force_wide", ctypes.c_int32)]
 
 
 Dims = ctypes.c_int64 * 3

@@ -110,6 +110,21 @@ thread_local const char* g_cur_name = nullptr;
 
 namespace qai {
 
+int kernel_block_limit(const void* fn)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, int>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto& kv : cache)
+        if (kv.first == fn)
+            return kv.second;
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, fn) != hipSuccess)
+        return 0;
+    cache.push_back({fn, at.maxThreadsPerBlock});
+    return at.maxThreadsPerBlock;
+}
+
 void prof_begin(const char* name, hipStream_t s)
 {
     if (!g_prof_on || g_prof_suppress)
@@ -171,6 +186,7 @@ int tuning_to_abi(const Tuning& t, qai_tuning* out)
     out->seed_rows = t.seed_ty;
     out->seed_planes = t.seed_tz;
     out->window_threads = t.env_threads;
+    out->force_wide = t.force_wide;
     return QAI_OK;
 }
 
@@ -351,17 +367,21 @@ int qai_copy_probe(const void* src, void* dst, size_t n_words, void* stream)
         size_t blocks = (n16 + 255) / 256;
         if (blocks > 8192)
             blocks = 8192;
-        hipLaunchKernelGGL(k_copy, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, (const uint4*)src,
-                           (uint4*)dst, n16);
+        const hipError_t e = qai::launch_checked(k_copy, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream,
+                                                 (const uint4*)src, (uint4*)dst, n16);
+        if (e != hipSuccess)
+            return fail_hip(e, "copy launch");
     }
     const size_t from = n16 * 4;
     if (from < n_words) {
         const size_t rest = n_words - from;
-        hipLaunchKernelGGL(k_copy_tail, dim3((uint32_t)((rest + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                           (const uint32_t*)src, (uint32_t*)dst, from, n_words);
+        const hipError_t e =
+            qai::launch_checked(k_copy_tail, dim3((uint32_t)((rest + 255) / 256)), dim3(256), 0,
+                                (hipStream_t)stream, (const uint32_t*)src, (uint32_t*)dst, from, n_words);
+        if (e != hipSuccess)
+            return fail_hip(e, "copy launch");
     }
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? QAI_OK : fail_hip(e, "copy launch");
+    return QAI_OK;
 }
 
 int qai_tuning_get(qai_tuning* out)
@@ -393,6 +413,8 @@ int qai_tuning_set(const qai_tuning* in)
             return fail(QAI_EINVAL, "seed_rows must be in [-1, 8] and seed_planes in [1, 4096]");
         if (in->window_threads < 64 || in->window_threads > 1024 || in->window_threads % 64)
             return fail(QAI_EINVAL, "window_threads must be a multiple of 64 in [64, 1024]");
+        if (in->force_wide != 0 && in->force_wide != 1)
+            return fail(QAI_EINVAL, "force_wide must be 0 or 1");
         for (int a = 1; a <= 2; ++a) {
             t.edt1_algo[a] = in->edt1_algo[a - 1];
             t.env_algo[a] = in->edt2_algo[a - 1];
@@ -403,6 +425,7 @@ int qai_tuning_set(const qai_tuning* in)
         t.seed_ty = in->seed_rows;
         t.seed_tz = in->seed_planes;
         t.env_threads = in->window_threads;
+        t.force_wide = in->force_wide;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune = t;

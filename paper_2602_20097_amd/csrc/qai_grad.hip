@@ -88,13 +88,11 @@ __global__ __launch_bounds__(kGradThreads) void k_grad_final(const double* __res
 hipError_t launch_backward(const float* g, const uint32_t* w1, const uint32_t* w2, int64_t n, float eb, float eta,
                            float power, double* partial, float* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_grad_partial, dim3(kGradBlocks), dim3(kGradThreads), 0, s, g, w1, w2, n, eb, eta, power,
-                       partial);
-    hipError_t e = hipGetLastError();
+    const hipError_t e = launch_checked(k_grad_partial, dim3(kGradBlocks), dim3(kGradThreads), 0, s, g, w1, w2, n, eb,
+                                        eta, power, partial);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(kGradThreads), 0, s, partial, out);
-    return hipGetLastError();
+    return launch_checked(k_grad_final, dim3(1), dim3(kGradThreads), 0, s, (const double*)partial, out);
 }
 
 } // namespace qai

@@ -9,6 +9,32 @@
 
 namespace qai {
 
+// Largest workgroup the kernel fn was compiled for (its __launch_bounds__, as
+// the runtime reports it), cached per kernel; 0 if the runtime cannot tell.
+int kernel_block_limit(const void* fn);
+
+template <typename T>
+struct same_type {
+    using type = T;
+};
+
+// Every kernel of the library is launched through here: a workgroup larger
+// than the kernel's compiled bound (which the hardware would run with too few
+// registers per lane) is refused on the host with hipErrorInvalidConfiguration
+// before anything is enqueued.
+template <typename... P>
+hipError_t launch_checked(void (*fn)(P...), dim3 grid, dim3 block, size_t shm, hipStream_t s,
+                          typename same_type<P>::type... args)
+{
+    const int64_t threads = (int64_t)block.x * block.y * block.z;
+    const int lim = kernel_block_limit((const void*)fn);
+    if (lim <= 0 || threads > lim || threads < 1 || grid.x == 0)
+        return hipErrorInvalidConfiguration;
+    void* argv[] = {(void*)&args...};
+    const hipError_t e = hipLaunchKernel((const void*)fn, grid, block, argv, shm, s);
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
 // Stage A (+ the first EDT pass) or stage C (+ the first pass of the second
 // EDT): a 6-neighbour stencil marks the sites, then a scan along x gives each
 // voxel its nearest site on its x-line.
@@ -70,6 +96,7 @@ struct Tuning {
     int edt1_algo[3];     // env_algo for the first EDT
     int env_threads;      // threads per workgroup of the windowed variant
     int seed_ty, seed_tz; // x-lines (waves) and z-planes per workgroup of the seed passes
+    int force_wide;       // 1: take the 64-bit index/arithmetic variant wherever a kernel has one
 };
 
 void default_tuning(Tuning& t);

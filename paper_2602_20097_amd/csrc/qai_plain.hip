@@ -1173,8 +1173,7 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords, Fa
 template <bool BUF, bool BLK>
 static hipError_t launch_interp_search_t(const ZsArgs& a, int64_t blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_interp_own<BUF, BLK>), dim3((unsigned)blocks), dim3(256), 0, s, a);
-    const hipError_t e = hipGetLastError();
+    const hipError_t e = launch_checked(k_interp_own<BUF, BLK>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     if (e != hipSuccess)
         return e;
     const int64_t nwords = blocks * 16; // flag_bytes(n) / 8
@@ -1188,11 +1187,10 @@ static hipError_t launch_interp_search_t(const ZsArgs& a, int64_t blocks, hipStr
         fm.ncx = ((fm.zb + FAR_ZC - 1) / FAR_ZC + 7) / 8;
         grid = 8 * fm.pb * fm.ncx * FAR_ZC;
     }
-    hipLaunchKernelGGL((k_interp_far<BUF, BLK>), dim3((unsigned)grid), dim3(256), 0, s, a, nwords, fm);
-    return hipGetLastError();
+    return launch_checked(k_interp_far<BUF, BLK>, dim3((unsigned)grid), dim3(256), 0, s, a, nwords, fm);
 }
 
-static hipError_t launch_interp_search(const ZsArgs& a, hipStream_t s)
+static hipError_t launch_interp_search(const ZsArgs& a, bool force_wide, hipStream_t s)
 {
     const int64_t n = a.nx * a.ny * a.nz;
     if ((((uintptr_t)a.w1 | (uintptr_t)a.xq | (uintptr_t)a.out) & 15u) != 0)
@@ -1201,7 +1199,7 @@ static hipError_t launch_interp_search(const ZsArgs& a, hipStream_t s)
     if (blocks > 0x7FFFFFFF)
         return hipErrorInvalidValue;
     // buffer loads by 32-bit byte offset while gy (natural or blocked) stays below 2^31 bytes
-    const bool buf = word_capacity(a.nz, a.ny, a.nx) < ((int64_t)1 << 29);
+    const bool buf = word_capacity(a.nz, a.ny, a.nx) < ((int64_t)1 << 29) && !force_wide;
     if (buf)
         return a.blk ? launch_interp_search_t<true, true>(a, blocks, s) : launch_interp_search_t<true, false>(a, blocks, s);
     return a.blk ? launch_interp_search_t<false, true>(a, blocks, s) : launch_interp_search_t<false, false>(a, blocks, s);
@@ -1216,7 +1214,7 @@ static hipError_t launch_interp_search(const ZsArgs& a, hipStream_t s)
 // ties, right ones need to be strictly better), the choice Algorithm 1's
 // strict comparisons make.
 template <int AXIS>
-__global__ __launch_bounds__(256) void k_env_window(EnvArgs a)
+__global__ __launch_bounds__(1024) void k_env_window(EnvArgs a)
 {
     extern __shared__ __align__(16) uint32_t tile[];
     const int txl = a.tx_log2;
@@ -2375,6 +2373,7 @@ void default_tuning(Tuning& t)
     t.env_threads = 256;
     t.seed_ty = 0;
     t.seed_tz = 16;
+    t.force_wide = 0;
 }
 
 static hipError_t launch_seed_lines(int mode, const SeedArgs& in, hipStream_t s)
@@ -2391,10 +2390,9 @@ static hipError_t launch_seed_lines(int mode, const SeedArgs& in, hipStream_t s)
     const uint32_t grid = grid_cap(a.ngroups, 1u << 20);
     const size_t shm = per_wave * waves;
     if (mode == 0)
-        hipLaunchKernelGGL(k_seed_xscan<0>, dim3(grid), dim3(64 * waves), shm, s, a);
+        return launch_checked(k_seed_xscan<0>, dim3(grid), dim3(64 * waves), shm, s, a);
     else
-        hipLaunchKernelGGL(k_seed_xscan<1>, dim3(grid), dim3(64 * waves), shm, s, a);
-    return hipGetLastError();
+        return launch_checked(k_seed_xscan<1>, dim3(grid), dim3(64 * waves), shm, s, a);
 }
 
 static size_t slab_bytes(int64_t nx, int ty, int rows, int planes)
@@ -2422,14 +2420,13 @@ static hipError_t launch_seed_lane_t(const SeedArgs& in, int tz, hipStream_t s)
     const uintptr_t al = (uintptr_t)((MODE == 0) ? (const void*)in.xq : (const void*)in.w1) | (uintptr_t)in.wout;
     const dim3 g(grid), b(64 * WPB);
     if (taps)
-        hipLaunchKernelGGL((k_seed_lane<MODE, V, WPB, 1, true>), g, b, 0, s, A);
+        return launch_checked(k_seed_lane<MODE, V, WPB, 1, true>, g, b, 0, s, A);
     else if (V % 4 == 0 && in.nx % 4 == 0 && al % 16 == 0)
-        hipLaunchKernelGGL((k_seed_lane<MODE, V, WPB, VW4, false>), g, b, 0, s, A);
+        return launch_checked(k_seed_lane<MODE, V, WPB, VW4, false>, g, b, 0, s, A);
     else if (V % 2 == 0 && in.nx % 2 == 0 && al % 8 == 0)
-        hipLaunchKernelGGL((k_seed_lane<MODE, V, WPB, VW2, false>), g, b, 0, s, A);
+        return launch_checked(k_seed_lane<MODE, V, WPB, VW2, false>, g, b, 0, s, A);
     else
-        hipLaunchKernelGGL((k_seed_lane<MODE, V, WPB, 1, false>), g, b, 0, s, A);
-    return hipGetLastError();
+        return launch_checked(k_seed_lane<MODE, V, WPB, 1, false>, g, b, 0, s, A);
 }
 
 template <int MODE>
@@ -2474,10 +2471,9 @@ hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s, int want_ty,
             A.nbz = (in.nz + A.tz - 1) / A.tz;
             const uint32_t grid = grid_cap((uint64_t)(A.nby * A.nbz), 1u << 20);
             if (mode == 0)
-                hipLaunchKernelGGL((k_seed_seg<0, SEG>), dim3(grid), dim3(64 * SEG), lds, s, A);
+                return launch_checked(k_seed_seg<0, SEG>, dim3(grid), dim3(64 * SEG), lds, s, A);
             else
-                hipLaunchKernelGGL((k_seed_seg<1, SEG>), dim3(grid), dim3(64 * SEG), lds, s, A);
-            return hipGetLastError();
+                return launch_checked(k_seed_seg<1, SEG>, dim3(grid), dim3(64 * SEG), lds, s, A);
         }
     }
     int ty = want_ty > 0 ? want_ty : 4;
@@ -2500,10 +2496,9 @@ hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s, int want_ty,
     const uint32_t grid = grid_cap((uint64_t)(A.nby * A.nbz), 1u << 20);
     const int threads = 64 * (ty < 4 ? 4 : ty);
     if (mode == 0)
-        hipLaunchKernelGGL(k_seed_slab<0>, dim3(grid), dim3(threads), lds, s, A);
+        return launch_checked(k_seed_slab<0>, dim3(grid), dim3(threads), lds, s, A);
     else
-        hipLaunchKernelGGL(k_seed_slab<1>, dim3(grid), dim3(threads), lds, s, A);
-    return hipGetLastError();
+        return launch_checked(k_seed_slab<1>, dim3(grid), dim3(threads), lds, s, A);
 }
 
 static int default_tx_log2(int64_t n)
@@ -2526,8 +2521,7 @@ static hipError_t launch_band2_t(EnvArgs a, int lb, size_t lds, int threads, uin
             return e;
         attr_done = true;
     }
-    hipLaunchKernelGGL((k_env_band2<AXIS, M>), dim3(grid), dim3(threads), lds, s, a, lb);
-    return hipGetLastError();
+    return launch_checked(k_env_band2<AXIS, M>, dim3(grid), dim3(threads), lds, s, a, lb);
 }
 
 template <int AXIS>
@@ -2580,7 +2574,7 @@ static hipError_t launch_band2(int axis, EnvArgs a, const Tuning& t, hipStream_t
 }
 
 template <int AXIS, int C>
-static hipError_t launch_stream_t(EnvArgs a, hipStream_t s)
+static hipError_t launch_stream_t(EnvArgs a, bool force_wide, hipStream_t s)
 {
     // LDS ring: 6 bytes x C entries x 64 lanes per wave
     const int waves = C >= 32 ? 1 : 2;
@@ -2591,13 +2585,13 @@ static hipError_t launch_stream_t(EnvArgs a, hipStream_t s)
     const int64_t n = AXIS == 1 ? a.ny : a.nz;
     // site values are squared distances within the lower dimensions
     const int64_t gmax = (a.nx - 1) * (a.nx - 1) + (AXIS == 2 ? (a.ny - 1) * (a.ny - 1) : 0);
-    const bool small = n < 4096 && gmax < (1 << 24) && n * gmax + n * n * n / 4 < (int64_t)1 << 31;
+    const bool small =
+        !force_wide && n < 4096 && gmax < (1 << 24) && n * gmax + n * n * n / 4 < (int64_t)1 << 31;
     const dim3 grid(grid_cap(groups, 1u << 20)), blk(64 * waves);
     if (small)
-        hipLaunchKernelGGL((k_env_stream<AXIS, C, true>), grid, blk, lds, s, a);
+        return launch_checked(k_env_stream<AXIS, C, true>, grid, blk, lds, s, a);
     else
-        hipLaunchKernelGGL((k_env_stream<AXIS, C, false>), grid, blk, lds, s, a);
-    return hipGetLastError();
+        return launch_checked(k_env_stream<AXIS, C, false>, grid, blk, lds, s, a);
 }
 
 // Ring entries pack (g << hb) | row into 32 bits: hb covers the rows of the
@@ -2637,9 +2631,8 @@ static hipError_t launch_lane2_t(EnvArgs a, int hb, hipStream_t s)
     const int64_t nxb = (a.nx + 63) >> 6;
     a.ntiles = (uint64_t)(nxb * (AXIS == 1 ? a.nz : a.ny));
     const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
-    hipLaunchKernelGGL((k_env_lane2<AXIS, 32, WPB, BLK>), dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a,
+    return launch_checked(k_env_lane2<AXIS, 32, WPB, BLK>, dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a,
                        hb);
-    return hipGetLastError();
 }
 
 template <int AXIS>
@@ -2651,10 +2644,9 @@ static hipError_t launch_lane_t(EnvArgs a, int hb, bool small, hipStream_t s)
     const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
     const dim3 grid(grid_cap(groups, 1u << 20)), blk(64 * WPB);
     if (small)
-        hipLaunchKernelGGL((k_env_lane<AXIS, 32, true, WPB>), grid, blk, 0, s, a, hb);
+        return launch_checked(k_env_lane<AXIS, 32, true, WPB>, grid, blk, 0, s, a, hb);
     else
-        hipLaunchKernelGGL((k_env_lane<AXIS, 32, false, WPB>), grid, blk, 0, s, a, hb);
-    return hipGetLastError();
+        return launch_checked(k_env_lane<AXIS, 32, false, WPB>, grid, blk, 0, s, a, hb);
 }
 
 template <int AXIS>
@@ -2664,8 +2656,7 @@ static hipError_t launch_swin_t(EnvArgs a, hipStream_t s)
     const int64_t nxb = (a.nx + 63) >> 6;
     a.ntiles = (uint64_t)(nxb * (AXIS == 1 ? a.nz : a.ny));
     const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
-    hipLaunchKernelGGL((k_env_swin<AXIS, WPB>), dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a);
-    return hipGetLastError();
+    return launch_checked(k_env_swin<AXIS, WPB>, dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a);
 }
 
 // ----------------------------------------------- first EDT, y and z at once
@@ -2853,15 +2844,14 @@ __global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide, cons
         atomicOr(wide, 1u);
 }
 
-static hipError_t launch_edt1_yz(const EnvArgs& a, uint32_t* wide, const unsigned long long* b1count, hipStream_t s)
+static hipError_t launch_edt1_yz(const EnvArgs& a, uint32_t* wide, const unsigned long long* b1count,
+                                 bool force_wide, hipStream_t s)
 {
     const int64_t n = a.nx * a.ny * a.nz, nq = n / 4;
     const uint32_t grid = grid_cap((uint64_t)((nq + 1023) / 1024), 1u << 20);
-    if (n < ((int64_t)1 << 32))
-        hipLaunchKernelGGL(k_edt1_yz<uint32_t>, dim3(grid), dim3(256), 0, s, a, wide, b1count);
-    else
-        hipLaunchKernelGGL(k_edt1_yz<int64_t>, dim3(grid), dim3(256), 0, s, a, wide, b1count);
-    return hipGetLastError();
+    if (n < ((int64_t)1 << 32) && !force_wide)
+        return launch_checked(k_edt1_yz<uint32_t>, dim3(grid), dim3(256), 0, s, a, wide, b1count);
+    return launch_checked(k_edt1_yz<int64_t>, dim3(grid), dim3(256), 0, s, a, wide, b1count);
 }
 
 hipError_t launch_env(int axis, EnvArgs a, const Tuning& t, hipStream_t s)
@@ -2878,10 +2868,9 @@ hipError_t launch_env(int axis, EnvArgs a, const Tuning& t, hipStream_t s)
         const size_t shm = (size_t)(n << txl) * 4;
         const dim3 blk(t.env_threads > 0 ? t.env_threads : 256);
         if (axis == 1)
-            hipLaunchKernelGGL((k_env_window<1>), dim3(grid), blk, shm, s, a);
+            return launch_checked(k_env_window<1>, dim3(grid), blk, shm, s, a);
         else
-            hipLaunchKernelGGL((k_env_window<2>), dim3(grid), blk, shm, s, a);
-        return hipGetLastError();
+            return launch_checked(k_env_window<2>, dim3(grid), blk, shm, s, a);
     }
     if (t.env_algo[axis] == 2 && n <= 64 * 32)
         return launch_band2(axis, a, t, s);
@@ -2892,28 +2881,29 @@ hipError_t launch_env(int axis, EnvArgs a, const Tuning& t, hipStream_t s)
         bool small;
         if (lane2_geometry(axis, a, hb))
             return axis == 1 ? launch_lane2_t<1>(a, hb, s) : launch_lane2_t<2>(a, hb, s);
-        if (lane_geometry(axis, a, hb, small))
+        if (lane_geometry(axis, a, hb, small)) {
+            small = small && !t.force_wide;
             return axis == 1 ? launch_lane_t<1>(a, hb, small, s) : launch_lane_t<2>(a, hb, small, s);
+        }
     }
     const int cap = t.stream_cap[axis] <= 16 ? 16 : (t.stream_cap[axis] <= 32 ? 32 : 64);
+    const bool fw = t.force_wide != 0;
     if (axis == 1)
-        return cap == 16 ? launch_stream_t<1, 16>(a, s)
-                         : (cap == 32 ? launch_stream_t<1, 32>(a, s) : launch_stream_t<1, 64>(a, s));
-    return cap == 16 ? launch_stream_t<2, 16>(a, s)
-                     : (cap == 32 ? launch_stream_t<2, 32>(a, s) : launch_stream_t<2, 64>(a, s));
+        return cap == 16 ? launch_stream_t<1, 16>(a, fw, s)
+                         : (cap == 32 ? launch_stream_t<1, 32>(a, fw, s) : launch_stream_t<1, 64>(a, fw, s));
+    return cap == 16 ? launch_stream_t<2, 16>(a, fw, s)
+                     : (cap == 32 ? launch_stream_t<2, 32>(a, fw, s) : launch_stream_t<2, 64>(a, fw, s));
 }
 
 hipError_t launch_interp(const InterpArgs& a, hipStream_t s)
 {
     const uint64_t blocks = (uint64_t)((a.n + 255) / 256);
-    hipLaunchKernelGGL(k_interp, dim3(grid_cap(blocks, 1u << 20)), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return launch_checked(k_interp, dim3(grid_cap(blocks, 1u << 20)), dim3(256), 0, s, a);
 }
 
 hipError_t launch_clear(uint32_t* p, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_clear, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
-    return hipGetLastError();
+    return launch_checked(k_clear, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
 }
 
 // Which of the three word buffers ends up holding the final words of the
@@ -3014,7 +3004,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         ea.win = buf[1];
         ea.w = buf[0];
         prof_begin("edt1_yz", s);
-        QAI_TRY(launch_edt1_yz(ea, wide, b1count, s));
+        QAI_TRY(launch_edt1_yz(ea, wide, b1count, t.force_wide != 0, s));
         prof_end(s);
         // the fallback: the streaming outward search, the kernel that reads the gate
         Tuning tf = t1;
@@ -3086,7 +3076,7 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         const int nx2 = (c2 == o0) ? o1 : o0;
         ZsArgs za = {buf[w1], buf[c2], buf[nx2], p.xq, p.out, p.flags, p.nx, p.ny, p.nz, p.eta * p.eb, p.power, blk};
         prof_begin("edt2_z_interp", s);
-        QAI_TRY(launch_interp_search(za, s));
+        QAI_TRY(launch_interp_search(za, t.force_wide != 0, s));
         prof_end(s);
         p.w1_final = buf[w1];
         p.w2_final = buf[nx2];

@@ -11,43 +11,9 @@ import torch
 import oracle
 from paper_2602_20097_amd import synth
 
+from _parity import KEYS, assert_parity, gpu_run
+
 pytestmark = pytest.mark.gpu
-
-REL_TOL = 1e-6
-KEYS = ("q", "b1", "sb", "s", "d1sq", "b2", "d2sq")
-
-
-def gpu_run(xq, eb, eta=0.9, power=1.0):
-    """Both forms of the call: with every tap (all passes written out) and
-    without (the last EDT pass fused with step E); the outputs must agree
-    bit for bit."""
-    import paper_2602_20097_amd as qai
-    t = torch.from_numpy(np.ascontiguousarray(xq, np.float32)).cuda()
-    out, taps = qai.mitigate(t, eb, eta, power, taps=True)
-    plain = qai.mitigate(t, eb, eta, power)
-    torch.cuda.synchronize()
-    res = {k: v.cpu().numpy() for k, v in taps.items()}
-    res["out"] = out.cpu().numpy()
-    res["out_plain"] = plain.cpu().numpy()
-    return res
-
-
-def assert_parity(xq, eb, eta=0.9, power=1.0, label=""):
-    print(f"parity case {label} shape={xq.shape} eb={eb:.6g}", flush=True)
-    g = gpu_run(xq, eb, eta, power)
-    r = oracle.qai(xq, eb, eta, power)
-    for k in KEYS:
-        a, b = g[k], r[k]
-        if not np.array_equal(a.astype(np.int64), b.astype(np.int64)):
-            bad = np.argwhere(a.astype(np.int64) != b.astype(np.int64))
-            raise AssertionError(f"{label}: tap {k} differs at {len(bad)} voxels, first {bad[:5].tolist()}: "
-                                 f"gpu {a[tuple(bad[0])]} oracle {b[tuple(bad[0])]}")
-    assert np.array_equal(g["out_plain"].view(np.uint32), g["out"].view(np.uint32)), f"{label}: fused path differs"
-    err = np.abs(g["out"].astype(np.float64) - r["out"])
-    lim = REL_TOL * np.maximum(np.abs(r["out"]), eb)
-    assert (err <= lim).all(), f"{label}: out off by {err.max():.3g} (limit {lim[np.argmax(err - lim)]:.3g})"
-    np.testing.assert_allclose(g["w"], r["w"], rtol=0, atol=1e-6)
-    return g, r
 
 
 def test_w1_grf64():
@@ -271,13 +237,69 @@ def test_every_pass_algorithm_gives_the_same_transform():
     try:
         for xq, eb in cases:
             r = oracle.qai(xq, eb)
-            combos = [(a1, a2, 0) for a1 in (0, 1, 2, 4) for a2 in (0, 1, 2, 3, 4)] + [(4, 3, 4), (4, 3, 1), (4, 3, -1)]
+            # seed_rows: 0 register variant, 1..8 the LDS-slab variant (8: 512-thread
+            # workgroups), -1 one line per wave
+            combos = [(a1, a2, 0) for a1 in (0, 1, 2, 4) for a2 in (0, 1, 2, 3, 4)] + \
+                [(4, 3, r) for r in (8, 4, 2, 1, -1)]
             for a1, a2, rows in combos:
                 qai.set_tuning(edt1_algo=[a1, a1], edt2_algo=[a2, a2], seed_rows=rows)
                 print(f"tuning edt1 {a1} edt2 {a2} seed_rows {rows} shape {xq.shape}", flush=True)
                 g = gpu_run(xq, eb)
                 for k in KEYS:
                     assert np.array_equal(g[k].astype(np.int64), r[k].astype(np.int64)), (k, a1, a2, rows, xq.shape)
+    finally:
+        qai.set_tuning(None)
+    assert qai.get_tuning() == base
+
+
+def test_every_accepted_launch_setting_launches():
+    """Every setting qai_tuning_set accepts must launch: workgroup sizes of the
+    windowed search up to 1024 threads and LDS-slab seed passes of 1 to 8 waves
+    per workgroup (the launcher refuses a block beyond a kernel's compiled
+    bound on the host instead of launching it)."""
+    import paper_2602_20097_amd as qai
+    x32, xq, q, eb = synth.quantize(synth.grf((9, 70, 130), 3.0, 4321), 2e-2)
+    r = oracle.qai(xq, eb)
+    base = qai.get_tuning()
+    try:
+        for wt in (64, 128, 192, 256, 512, 1024):
+            qai.set_tuning(edt1_algo=[1, 1], edt2_algo=[1, 1], window_threads=wt)
+            assert_parity(xq, eb, label=f"window_threads {wt}", r=r)
+        qai.set_tuning(None)
+        for rows in range(-1, 9):
+            for planes in (1, 3, 16):
+                qai.set_tuning(seed_rows=rows, seed_planes=planes)
+                assert_parity(xq, eb, label=f"seed_rows {rows} seed_planes {planes}", r=r)
+    finally:
+        qai.set_tuning(None)
+    assert qai.get_tuning() == base
+
+
+@pytest.mark.parametrize("shape,rel", [((20, 36, 48), 2e-2), ((33, 40, 64), 5e-3), ((5, 70, 130), 2e-2),
+                                       ((96, 96, 96), None)])
+def test_wide_index_variants(shape, rel):
+    """force_wide = 1 takes the 64-bit variants that only fields beyond 2^29
+    words (the needed-voxel search by 64-bit index) or 2^32 voxels (the fused
+    first-EDT search) would take on their own, and the 64-bit arithmetic of the
+    streaming envelopes; they must compute the same transforms.  The last case
+    is dense B1 around a plateau, so the fused search hands over to the gated
+    separable passes."""
+    import paper_2602_20097_amd as qai
+    if rel is None:
+        rng = np.random.default_rng(31)
+        xq = rng.integers(-3, 4, size=shape).astype(np.float32)
+        xq[34:62, 34:62, 34:62] = 7.0
+        eb = 0.5
+    else:
+        x32, xq, q, eb = synth.quantize(synth.grf(shape, 3.0, 11 + sum(shape)), rel)
+    r = oracle.qai(xq, eb)
+    base = qai.get_tuning()
+    try:
+        for cfg in (dict(force_wide=1), dict(force_wide=1, edt1_algo=[0, 0], edt2_algo=[0, 0]),
+                    dict(force_wide=1, edt2_algo=[3, -1])):
+            qai.set_tuning(None)
+            qai.set_tuning(**cfg)
+            assert_parity(xq, eb, label=f"wide {cfg} {shape}", r=r)
     finally:
         qai.set_tuning(None)
     assert qai.get_tuning() == base

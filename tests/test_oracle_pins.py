@@ -296,3 +296,61 @@ def test_table2_relaxed_bound():
         assert rel <= bound * (1 + 1e-5)
         worst = max(worst, rel)
     assert worst >= 0.9 * bound
+
+
+# ------------------------------------------------- generalised IDW power p
+def test_idw_power_closed_forms_on_the_w8_bands():
+    """Step E's weight generalised to w = k1^-p / (k1^-p + k2^-p) (the
+    differentiable form; p = 1 is Section V-E).  Inside an interior band of the
+    W = 8 staircase the distances are d1 = (0,1,2,3,3,2,1,0) and
+    d2 = (3,2,1,0,0,1,2,3) (test_w8_bands_closed_form), so for p = 2 the weight
+    is d2^2 / (d1^2 + d2^2) = (1, 4/5, 1/5, 0, 0, 1/5, 4/5, 1) and for p = 1/2
+    it is sqrt(d2) / (sqrt(d1) + sqrt(d2)); p = 1 gives the default call."""
+    n = 32
+    k = np.arange(n)
+    q = k // 8
+    xq = q.astype(np.float32)[None, None, :]
+    band = np.arange(8, 16)
+    s_band = np.array([-1, -1, -1, -1, 1, 1, 1, 1])
+    d1 = np.array([0, 1, 2, 3, 3, 2, 1, 0], float)
+    d2 = np.array([3, 2, 1, 0, 0, 1, 2, 3], float)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        expect = {
+            2.0: np.array([1, 4 / 5, 1 / 5, 0, 0, 1 / 5, 4 / 5, 1]),
+            0.5: np.where(d1 == 0, 1.0, np.where(d2 == 0, 0.0, np.sqrt(d2) / (np.sqrt(d1) + np.sqrt(d2)))),
+            1.0: np.where(d1 == 0, 1.0, np.where(d2 == 0, 0.0, d2 / (d1 + d2))),
+        }
+    default = oracle.qai(xq, 0.5)
+    for p, w in expect.items():
+        for eta in (0.9, 0.5):
+            r = oracle.qai(xq, 0.5, eta, p)
+            np.testing.assert_allclose(r["w"][0, 0, band], w, rtol=0, atol=1e-15)
+            e = float(np.float32(eta)) * 0.5
+            np.testing.assert_allclose(r["out"][0, 0, band] - xq[0, 0, band], w * s_band * e, rtol=0, atol=1e-15)
+    assert np.array_equal(oracle.qai(xq, 0.5, 0.9, 1.0)["out"], default["out"])
+
+
+def test_idw_power_symmetry_and_limits():
+    """For every p, swapping the two distances turns w into 1 - w, equal
+    distances give w = 1/2, and w grows with p where k1 < k2 (it tends to the
+    nearest-boundary indicator as p grows).  Checked on a smooth field, where
+    the pairs (k1, k2) come from the oracle's own transforms."""
+    x32, xq, q, eb = small_field(3)
+    base = oracle.qai(xq, eb)
+    d1, d2 = base["d1sq"].astype(float), base["d2sq"].astype(float)
+    gen = (d1 > 0) & (d2 > 0)
+    assert gen.sum() > 100
+    k1, k2 = np.sqrt(d1[gen]), np.sqrt(d2[gen])
+    prev = None
+    for p in (0.25, 0.5, 1.0, 2.0, 4.0):
+        w = oracle.qai(xq, eb, 0.9, p)["w"][gen]
+        # the weight depends on k1/k2 only: w = 1 / (1 + (k1/k2)^p)
+        np.testing.assert_allclose(w, 1.0 / (1.0 + (k1 / k2) ** p), rtol=1e-12, atol=0)
+        np.testing.assert_allclose(w[k1 == k2], 0.5, rtol=0, atol=1e-15)
+        if prev is not None:
+            closer = k1 < k2
+            assert (w[closer] >= prev[closer] - 1e-15).all()
+            assert (w[~closer & (k1 != k2)] <= prev[~closer & (k1 != k2)] + 1e-15).all()
+        prev = w
+    # the p = 1 weight of Section V-E, (1/k1) / (1/k1 + 1/k2) = k2 / (k1 + k2)
+    np.testing.assert_allclose(base["w"][gen], k2 / (k1 + k2), rtol=1e-12, atol=0)
