@@ -128,6 +128,25 @@ int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const q
 int qai_backward(const float* grad_out, void* ws_saved, size_t ws_bytes, const int64_t dims[3],
                  float eb, const qai_params* params, float* grad_params, void* stream);
 
+/* qai_mitigate_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  The same post-pass and result as qai_mitigate_ex with
+ * taps = NULL, but the workspace is a fixed device array inside the library of
+ * QAI_NOALLOC_SCRATCH_BYTES (256 MiB) on each GPU it runs on, held until the
+ * process ends; nothing is allocated or freed.
+ *   field, dims, eb, out, stream  as for qai_mitigate
+ *   params                        as for qai_mitigate_ex (NULL = defaults)
+ * Fields whose qai_workspace_bytes(dims) exceeds QAI_NOALLOC_SCRATCH_BYTES
+ * (about 22 million voxels) are rejected with QAI_ENOWS before anything is
+ * enqueued.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (each call clears the words it needs cleared with a
+ * kernel): calls that overlap on one GPU, on different streams or threads,
+ * race and must be serialised by the caller.  The status words live in that
+ * array too, so qai_device_status does not apply to these calls. */
+#define QAI_NOALLOC_SCRATCH_BYTES (256u << 20)
+int qai_mitigate_noalloc(const float* field, const int64_t dims[3], float eb, const qai_params* params, float* out,
+                         void* stream);
+
 /* qai_device_status -- synchronises stream and reports the status bits the
  * last run on workspace ws raised (QAI_STATUS_*). */
 int qai_device_status(const void* ws, void* stream, uint32_t* flags);

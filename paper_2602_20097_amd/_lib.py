@@ -20,6 +20,7 @@ ERRORS = {-1: "QAI_EINVAL", -2: "QAI_EDIMS", -3: "QAI_ENOWS", -4: "QAI_EHIP", -5
           -6: "QAI_ESTATE"}
 QAI_STATUS_QRANGE = 0x1
 MAX_EXTENT = 16384
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class QAIError(RuntimeError):
@@ -47,7 +48,7 @@ Dims = ctypes.c_int64 * 3
 EXPORTS = ["qai_mitigate", "qai_workspace_bytes", "qai_mitigate_ex", "qai_backward", "qai_device_status",
            "qai_last_error", "qai_batch_workspace_bytes", "qai_batch_plan_create", "qai_batch_plan_launch",
            "qai_batch_plan_launch_per_field", "qai_batch_plan_tuning", "qai_batch_plan_destroy", "qai_copy_probe",
-           "qai_profile_enable", "qai_stage_times", "qai_tuning_get", "qai_tuning_set"]
+           "qai_profile_enable", "qai_stage_times", "qai_tuning_get", "qai_tuning_set", "qai_mitigate_noalloc"]
 
 _lib = None
 
@@ -63,6 +64,7 @@ def load(path=LIB_PATH):
     lib = ctypes.CDLL(path)
     P, I64P, F, SZ, I = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_float, ctypes.c_size_t, ctypes.c_int
     lib.qai_mitigate.argtypes = [P, I64P, F, P, P]
+    lib.qai_mitigate_noalloc.argtypes = [P, I64P, F, ctypes.POINTER(Params), P, P]
     lib.qai_workspace_bytes.argtypes = [I64P]
     lib.qai_workspace_bytes.restype = SZ
     lib.qai_mitigate_ex.argtypes = [P, I64P, F, ctypes.POINTER(Params), P, SZ, P, ctypes.POINTER(Taps), P]

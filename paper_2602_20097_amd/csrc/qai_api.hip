@@ -262,6 +262,40 @@ __global__ void k_copy_tail(const uint32_t* src, uint32_t* dst, size_t from, siz
         dst[i] = src[i];
 }
 
+// Fixed device scratch of the allocation-free entry point: the workspace of
+// qai_mitigate_noalloc.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code the name stands for no device
+// address; the address is taken once per device with hipGetSymbolAddress.
+__device__ __align__(256) unsigned char scratch[QAI_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on the first
+// call on that device, with that device current).
+int scratch_on_current_device(void** ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(QAI_ENODEV, "no usable GPU: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(QAI_ENODEV, "device ordinal %d beyond the %d the library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return fail_hip(e, "hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p & 255u) != 0)
+            return fail(QAI_EHIP, "scratch symbol has no 256-byte aligned device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return QAI_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -308,6 +342,24 @@ int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out
     if (rc == QAI_OK && e != hipSuccess)
         return fail_hip(e, "hipFreeAsync");
     return rc;
+}
+
+int qai_mitigate_noalloc(const float* field, const int64_t dims[3], float eb, const qai_params* params, float* out,
+                         void* stream)
+{
+    g_err.clear();
+    int64_t n;
+    int rc = check_dims(dims, &n);
+    if (rc)
+        return rc;
+    const size_t need = qai_workspace_bytes(dims);
+    if (need > (size_t)QAI_NOALLOC_SCRATCH_BYTES)
+        return fail(QAI_ENOWS, "field needs %zu bytes of workspace; the fixed scratch holds %zu", need,
+                    (size_t)QAI_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    if ((rc = scratch_on_current_device(&ws)))
+        return rc;
+    return plain_checked(field, dims, eb, params, ws, (size_t)QAI_NOALLOC_SCRATCH_BYTES, out, nullptr, stream);
 }
 
 int qai_device_status(const void* ws, void* stream, uint32_t* flags)

@@ -76,6 +76,12 @@ def test_argument_errors_are_caught_on_the_host(lib):
     assert lib.qai_mitigate(FAKE, _lib.Dims(4, 0, 4), ctypes.c_float(0.1), FAKE, None) == -2
     assert lib.qai_backward(None, FAKE, 1 << 30, _lib.Dims(4, 4, 4), ctypes.c_float(0.1), None, FAKE, None) == -1
     assert lib.qai_copy_probe(None, FAKE, 4, None) == -1
+    # the allocation-free entry point: size limit of its fixed scratch, bad dims
+    big = _lib.Dims(512, 512, 512)
+    assert lib.qai_workspace_bytes(big) > _lib.NOALLOC_SCRATCH_BYTES
+    assert lib.qai_mitigate_noalloc(FAKE, big, ctypes.c_float(0.1), None, FAKE, None) == -3
+    assert "scratch" in lib.qai_last_error().decode()
+    assert lib.qai_mitigate_noalloc(FAKE, _lib.Dims(4, 0, 4), ctypes.c_float(0.1), None, FAKE, None) == -2
 
 
 def test_no_device_is_reported_without_a_launch(lib):
