@@ -1,7 +1,7 @@
 """Benchmark of the QAI post-pass on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--no-cpu-baseline] [--no-regime]
+                    [--no-cpu-baseline] [--no-regime] [--no-extra]
 
 A step is one full post-pass (Algorithm 4: boundary/sign stencil, two exact
 EDTs, interpolation and compensation) over one synthetic field already
@@ -10,14 +10,31 @@ resident in HBM.  The workload defaults to the 512^3 Gaussian random field
 of the paper's per-rank JHTDB blocks (Section VII-E2).
 
 Prints ONE JSON line on stdout (everything else goes to stderr):
-value = field GB/s = 4 bytes x voxels x steps / elapsed; roofline = the
-dominant kernel's algorithmic bytes per launch / its mean duration (HIP
-events on the launch stream over the timed region) against 8 TB/s;
-cpu_baseline = the CPU oracle timed on a bounded slab of the same field.
+* value = field GB/s = 4 bytes x voxels x steps / elapsed (host clock around
+  exactly K steps, bracketed by device synchronisation; no stage timing on);
+* roofline = the dominant kernel's algorithmic bytes per launch / its mean
+  duration (HIP events on the launch stream, from a separate staged run)
+  against 8 TB/s;
+* pipeline = the whole pass against the roofline: algorithmic (the 56 B/voxel
+  budget of two separable 3-pass EDTs in 3-D, 40 B in 2-D, and the bytes this
+  design must move), measured (rocprofv3 FETCH/WRITE bytes of every stage,
+  while the kernels are the ones measured) and against a copy kernel;
+* workloads = the other configurations of the metric (the 256x384x384 field at
+  three bounds, the 2-D 1800x3600 field, the 256^3 field of the
+  differentiable form with its adjoint, the 64^3 field), each with its regime;
+* quality = SSIM and PSNR on the GPU before and after the pass (also per
+  workload: the eb-distortion sweep of the 256x384x384 field), and the metric
+  kernels' rate;
+* blocks = the paper's block strategies (embarrassingly parallel, approximate)
+  on 2 x 2 x 2 blocks beside the exact pass: time and quality;
+* batched = the 48-field uneven batch, one graph launch vs per-field launches;
+* cpu_baseline = the CPU oracle on the host's cores and on one core.
 """
 import argparse
+import ctypes
 import json
 import os
+import platform
 import sys
 import time
 
@@ -28,6 +45,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QAI post-pass GB/s of FP32 field and % HBM roofline, plain vs batched, 1 GPU"
 HBM_PEAK_GBPS = 8000.0
+# Byte budget of the separable pass: read x', write out, and the word round
+# trips of two EDTs of three passes each (two in 2-D).
+BUDGET_3D, BUDGET_2D = 56, 40
+# The paper's CPU throughput (Section VII-E2, weak scaling, 64 ranks on two
+# nodes of 2x AMD EPYC 7702, 512^3 FP32 blocks): 695.93 MB/s with the
+# embarrassingly parallel decomposition, i.e. about 10.9 MB/s per core.
+PAPER_CPU = {"mb_per_s": 695.93, "ranks": 64, "mb_per_s_per_core": round(695.93 / 64, 2),
+             "hardware": "2 nodes x 2x AMD EPYC 7702 (64 cores each), one core per rank",
+             "workload": "512^3 FP32 blocks of a turbulence field, embarrassingly parallel variant"}
 
 # Algorithmic HBM bytes per voxel of each stage (reads + writes of the
 # arrays the stage must touch once): the post-pass moves 44 B/voxel in 3-D.
@@ -46,9 +72,38 @@ STAGE_BYTES = {
     "clear": 0,
 }
 
+EXTRA_WORKLOADS = ["modes256x384x384_eb1e-4", "modes256x384x384_eb1e-3", "modes256x384x384_eb1e-2",
+                   "grf2d_1800x3600_k11/3_eb1e-3", "grf256_k3_eb5e-3", "grf64_k3_eb1e-2"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def budget(shape):
+    return BUDGET_3D if shape[0] > 1 else BUDGET_2D
+
+
+def timed_steps(fn, steps, warmup, stream):
+    """Warm up, then time exactly `steps` calls: host clock between two device
+    synchronisations, plus one HIP event pair per step on the launch stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    marks[0].record(stream)
+    for k in range(steps):
+        fn()
+        marks[k + 1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(steps))
+    trimmed = step_ms[1:-1] if len(step_ms) > 2 else step_ms
+    return elapsed, {"median": float(np.median(step_ms)), "trimmed_mean": float(np.mean(trimmed)),
+                     "min": step_ms[0], "max": step_ms[-1]}
 
 
 def main():
@@ -59,10 +114,8 @@ def main():
     ap.add_argument("--workload", default="grf512_k11/3_eb1e-3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-regime", action="store_true")
-    ap.add_argument("--batched", action="store_true",
-                    help="also time the 48-field uneven batch (graph launch vs per-field launches)")
-    ap.add_argument("--grad", action="store_true",
-                    help="also time forward + adjoint on the 256^3 field of the differentiable form")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline only: skip the other workloads, the batch and the adjoint")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -91,68 +144,43 @@ def main():
     ws = qai.new_workspace(shape, dev)
     stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        qai.mitigate(field, eb, out=out, workspace=ws)
-    torch.cuda.synchronize()
-    log(f"warmup {args.warmup} done")
-
     # copy-kernel bandwidth (the achievable HBM rate) on buffers of the field's size
     src = torch.empty(nvox, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     qai.copy_probe(src, dst)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        qai.copy_probe(src, dst)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbps = 10 * 8.0 * nvox / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    copy_s, _ = timed_steps(lambda: qai.copy_probe(src, dst), 10, 1, stream)
+    copy_gbps = 10 * 8.0 * nvox / copy_s / 1e9
     del src, dst
 
-    # timed region: K full post-passes, stage and step events on the launch stream
-    qai.profile(True)
-    qai.stage_times(reset=True)
-    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    marks[0].record(stream)
-    for k in range(args.steps):
-        qai.mitigate(field, eb, out=out, workspace=ws)
-        marks[k + 1].record(stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    step_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps))
-    trimmed = step_ms[1:-1] if len(step_ms) > 2 else step_ms
-    stages = qai.stage_times(reset=True)
-    qai.profile(False)
+    # timed region: exactly K full post-passes, no stage timing
+    run = lambda: qai.mitigate(field, eb, out=out, workspace=ws)  # noqa: E731
+    elapsed, step = timed_steps(run, args.steps, args.warmup, stream)
     ms_step = elapsed * 1e3 / args.steps
     value = 4.0 * nvox * args.steps / elapsed / 1e9
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, field {value:.1f} GB/s")
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, field {value:.1f} GB/s "
+        f"(device median {step['median']:.3f} ms)")
 
+    # a separate run with per-stage HIP events (for the kernel roofline)
+    qai.profile(True)
+    qai.stage_times(reset=True)
+    for _ in range(args.steps):
+        run()
+    stages = qai.stage_times(reset=True)
+    qai.profile(False)
     per_launch = {k: v / args.steps for k, v in stages.items()}
     dom = max((k for k in per_launch if STAGE_BYTES.get(k, 0) > 0), key=lambda k: per_launch[k])
     dom_ms = per_launch[dom]
     dom_bytes = STAGE_BYTES[dom] * nvox
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    total_alg = sum(STAGE_BYTES.get(k, 0) for k in per_launch) * nvox
-    stage_sum_ms = sum(per_launch.values())
+    own_alg = sum(STAGE_BYTES.get(k, 0) for k in per_launch) * nvox
     for k, v in per_launch.items():
         bw = STAGE_BYTES.get(k, 0) * nvox / (v * 1e-3) / 1e9 if v > 0 else 0.0
         log(f"  stage {k:16s} {v * 1e3:9.1f} us  {bw:8.1f} GB/s alg")
 
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tfile):
-        try:
-            with open(tfile) as fh:
-                tr = json.load(fh)
-            key = f"{args.workload}:{dom}"
-            if key in tr and tr[key].get("kernel_rev") == kernel_rev():
-                traffic = tr[key]["bytes_per_launch"]
-        except Exception:
-            traffic = None
-
+    traffic, measured = read_traffic(args.workload, list(per_launch))
+    dom_traffic = traffic.get(dom) if traffic else None
+    bud = budget(shape) * nvox
+    t_s = ms_step * 1e-3
     res = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -169,27 +197,43 @@ def main():
         "config": {"workload": args.workload, "shape": list(shape), "voxels": nvox, "eb": eb,
                    "eb_rel": synth.WORKLOADS[args.workload]["rel"], "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": dom,
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": dom_traffic, "kernel": dom,
                      "kernel_ms": round(dom_ms, 4), "alg_bytes_per_launch": dom_bytes},
-        "pipeline": {"alg_bytes_per_voxel": total_alg // nvox,
-                     "alg_GBps": round(total_alg / (ms_step * 1e-3) / 1e9, 1),
-                     "frac_of_peak": round(total_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                     "frac_of_copy": round(total_alg / (ms_step * 1e-3) / 1e9 / copy_gbps, 4),
-                     "copy_GBps": round(copy_gbps, 1), "stage_sum_ms": round(stage_sum_ms, 4),
-                     "stages_us": {k: round(v * 1e3, 1) for k, v in per_launch.items()},
-                     "step_ms_median": round(float(np.median(step_ms)), 4),
-                     "step_ms_trimmed_mean": round(float(np.mean(trimmed)), 4)},
+        "pipeline": {
+            "budget_bytes_per_voxel": budget(shape),
+            "frac_of_peak_budget": round(bud / t_s / 1e9 / HBM_PEAK_GBPS, 4),
+            "alg_bytes_per_voxel": own_alg // nvox,
+            "frac_of_peak_alg": round(own_alg / t_s / 1e9 / HBM_PEAK_GBPS, 4),
+            "measured_bytes_per_voxel": round(measured / nvox, 2) if measured else None,
+            "frac_of_peak_measured": round(measured / t_s / 1e9 / HBM_PEAK_GBPS, 4) if measured else None,
+            "measured_within_guard": (measured <= 1.25 * bud) if measured else None,
+            "frac_of_copy_budget": round(bud / t_s / 1e9 / copy_gbps, 4),
+            "copy_GBps": round(copy_gbps, 1),
+            "stages_us": {k: round(v * 1e3, 1) for k, v in per_launch.items()},
+            "stage_sum_ms": round(sum(per_launch.values()), 4),
+            "step_ms_median": round(step["median"], 4),
+            "step_ms_trimmed_mean": round(step["trimmed_mean"], 4)},
     }
-
     if not args.no_regime:
         res["regime"] = regime_stats(qai, field, x32, eb, dev)
+    if not args.no_extra:
+        res["quality"] = bench_quality(qai, field, out, x32, dev, max(5, args.steps // 2))
+        if shape[0] > 1:
+            del ws
+            torch.cuda.empty_cache()
+            res["blocks"] = bench_blocks(qai, field, x32, eb, dev, ms_step, max(3, args.steps // 4))
+    del field, out
+    torch.cuda.empty_cache()
 
-    if args.grad:
-        res["differentiable"] = bench_grad(qai, synth, dev, args.steps, args.warmup)
-    if args.batched:
-        del field, out, ws
+    if not args.no_extra:
+        res["workloads"] = {}
+        for name in EXTRA_WORKLOADS:
+            res["workloads"][name] = bench_workload(qai, synth, dev, name, max(5, args.steps // 2), args.no_regime)
+            torch.cuda.empty_cache()
+        res["differentiable"] = bench_grad(qai, synth, dev, max(5, args.steps // 2))
         torch.cuda.empty_cache()
         res["batched"] = bench_batched(qai, synth, dev, max(3, args.steps // 4))
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(xq, eb)
@@ -197,19 +241,99 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def _time(fn, reps, stream):
+def read_traffic(workload, stages):
+    """Stage bytes from profiles/traffic.json (rocprofv3 FETCH_SIZE/WRITE_SIZE,
+    scaled by the copy probe), used only while the kernel sources hash to the
+    revision they were measured on.  Returns ({stage: bytes}, pass total or None)."""
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tfile):
+        return {}, None
+    try:
+        with open(tfile) as fh:
+            tr = json.load(fh)
+    except Exception:
+        return {}, None
+    rev = kernel_rev()
+    out = {}
+    for st in stages:
+        e = tr.get(f"{workload}:{st}")
+        if e and e.get("kernel_rev") == rev:
+            out[st] = e["bytes_per_launch"]
+    total = sum(out.values()) if all(st in out for st in stages) else None
+    return out, total
+
+
+def bench_quality(qai, field, out, x32, dev, reps):
+    """SSIM (Eq. 3) and PSNR (Eq. 4) on the GPU of the decompressed and the
+    compensated field against the original, and the metric kernels' rate
+    (two passes over two fields: 16 B/voxel)."""
     import torch
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    a.record(stream)
-    for _ in range(reps):
-        fn()
-    b.record(stream)
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps
+    x = torch.from_numpy(x32).to(dev)
+    before = qai.quality(x, field)
+    after = qai.quality(x, out)
+    s = torch.cuda.current_stream()
+    el, step = timed_steps(lambda: qai.quality(x, out, sync=False), reps, 1, s)
+    ms = el * 1e3 / reps
+    n = x.numel()
+    log(f"quality: SSIM {before['ssim']:.4f} -> {after['ssim']:.4f}, PSNR {before['psnr']:.2f} -> "
+        f"{after['psnr']:.2f} dB; metric pass {ms:.3f} ms")
+    return {"ssim_before": round(before["ssim"], 6), "ssim_after": round(after["ssim"], 6),
+            "psnr_before": round(before["psnr"], 4), "psnr_after": round(after["psnr"], 4),
+            "metric_ms": round(ms, 4), "metric_GBps_alg": round(16.0 * n / (ms * 1e-3) / 1e9, 1),
+            "metric_frac_of_peak": round(16.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
 
 
-def bench_grad(qai, synth, dev, steps, warmup):
+def bench_blocks(qai, field, x32, eb, dev, exact_ms, reps, blocks=(2, 2, 2)):
+    """The paper's block strategies (Section VI-B) with the field cut into
+    2 x 2 x 2 blocks: time and quality of embarrassingly parallel and
+    approximate beside the exact (whole-field) pass."""
+    import torch
+    x = torch.from_numpy(x32).to(dev)
+    s = torch.cuda.current_stream()
+    res = {"blocks": list(blocks), "exact_ms": round(exact_ms, 4)}
+    exact = qai.mitigate(field, eb)
+    q = qai.quality(x, exact)
+    res["exact_ssim"], res["exact_psnr"] = round(q["ssim"], 6), round(q["psnr"], 4)
+    for mode in ("ep", "approximate"):
+        o = torch.empty_like(field)
+        el, _ = timed_steps(lambda: qai.mitigate_blocks(field, eb, blocks, mode=mode, out=o), reps, 1, s)
+        q = qai.quality(x, o)
+        differ = float((o != exact).float().mean())
+        res[mode] = {"ms": round(el * 1e3 / reps, 4), "ssim": round(q["ssim"], 6), "psnr": round(q["psnr"], 4),
+                     "frac_voxels_differing_from_exact": round(differ, 6)}
+        log(f"blocks {mode}: {el * 1e3 / reps:.3f} ms, SSIM {q['ssim']:.5f}, PSNR {q['psnr']:.3f}, "
+            f"{differ:.4%} of voxels differ from the exact pass")
+    return res
+
+
+def bench_workload(qai, synth, dev, name, steps, no_regime):
+    import torch
+    x32, xq, q, eb = synth.make_workload(name)
+    n = int(np.prod(xq.shape))
+    t = torch.from_numpy(xq).to(dev)
+    out = torch.empty_like(t)
+    ws = qai.new_workspace(t.shape, dev)
+    s = torch.cuda.current_stream()
+    elapsed, step = timed_steps(lambda: qai.mitigate(t, eb, out=out, workspace=ws), steps, 3, s)
+    ms = elapsed * 1e3 / steps
+    bud = budget(xq.shape) * n
+    entry = {"shape": list(xq.shape), "voxels": n, "eb": eb, "ms": round(ms, 4),
+             "device_ms_median": round(step["median"], 4),
+             "GBps": round(4.0 * n / (ms * 1e-3) / 1e9, 2),
+             "budget_bytes_per_voxel": budget(xq.shape),
+             "frac_of_peak_budget": round(bud / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    if not no_regime:
+        entry["regime"] = regime_stats(qai, t, x32, eb, dev)
+    if min(xq.shape[1:]) >= 2:
+        x = torch.from_numpy(x32).to(dev)
+        qb, qa = qai.quality(x, t), qai.quality(x, out)
+        entry["quality"] = {"ssim_before": round(qb["ssim"], 6), "ssim_after": round(qa["ssim"], 6),
+                            "psnr_before": round(qb["psnr"], 4), "psnr_after": round(qa["psnr"], 4)}
+    log(f"workload {name}: {ms:.3f} ms, {entry['GBps']} GB/s, {entry['frac_of_peak_budget']:.3f} of peak")
+    return entry
+
+
+def bench_grad(qai, synth, dev, steps):
     """Forward (workspace kept) + adjoint on the 256^3 differentiable-form field."""
     import torch
     name = "grf256_k3_eb5e-3"
@@ -220,14 +344,15 @@ def bench_grad(qai, synth, dev, steps, warmup):
     ws = qai.new_workspace(t.shape, dev)
     g = torch.randn_like(t)
     s = torch.cuda.current_stream()
-    for _ in range(warmup):
-        qai.mitigate(t, eb, out=out, workspace=ws)
-        qai.backward(g, ws, t.shape, eb)
-    fwd = _time(lambda: qai.mitigate(t, eb, out=out, workspace=ws), steps, s)
-    bwd = _time(lambda: qai.backward(g, ws, t.shape, eb), steps, s)
+    qai.mitigate(t, eb, out=out, workspace=ws)
+    f_el, _ = timed_steps(lambda: qai.mitigate(t, eb, out=out, workspace=ws), steps, 2, s)
+    b_el, bstep = timed_steps(lambda: qai.backward(g, ws, t.shape, eb), steps, 2, s)
+    fwd, bwd = f_el * 1e3 / steps, b_el * 1e3 / steps
     log(f"differentiable {name}: forward {fwd:.3f} ms, adjoint {bwd:.3f} ms")
     return {"workload": name, "voxels": n, "forward_ms": round(fwd, 4), "adjoint_ms": round(bwd, 4),
-            "adjoint_GBps_alg": round(12.0 * n / (bwd * 1e-3) / 1e9, 1)}
+            "adjoint_device_ms_median": round(bstep["median"], 4),
+            "adjoint_GBps_alg": round(12.0 * n / (bwd * 1e-3) / 1e9, 1),
+            "adjoint_frac_of_peak": round(12.0 * n / (bwd * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
 
 
 def bench_batched(qai, synth, dev, reps):
@@ -244,18 +369,22 @@ def bench_batched(qai, synth, dev, reps):
     log(f"batch of {len(fields)} fields, {nvox} voxels, generated in {time.time() - t0:.1f}s")
     plan = qai.BatchPlan(fields, ebs, autotune=True)
     s = torch.cuda.current_stream()
-    plan.launch()
-    plan.launch_per_field()
-    graph_ms = _time(plan.launch, reps, s)
-    per_ms = _time(plan.launch_per_field, reps, s)
+    g_el, gstep = timed_steps(plan.launch, reps, 1, s)
+    p_el, _ = timed_steps(plan.launch_per_field, reps, 1, s)
+    graph_ms, per_ms = g_el * 1e3 / reps, p_el * 1e3 / reps
     tunes = {}
     for i, f in enumerate(fields):
         tunes.setdefault("x".join(map(str, f.shape)), plan.tuning(i))
     plan.close()
+    bud = BUDGET_3D * nvox
     log(f"batched: graph {graph_ms:.2f} ms, per-field launches {per_ms:.2f} ms")
-    return {"fields": len(fields), "voxels": nvox, "graph_ms": round(graph_ms, 3), "per_field_ms": round(per_ms, 3),
+    return {"fields": len(fields), "voxels": nvox, "graph_ms": round(graph_ms, 3),
+            "graph_device_ms_median": round(gstep["median"], 3), "per_field_ms": round(per_ms, 3),
             "value": round(4.0 * nvox / (graph_ms * 1e-3) / 1e9, 2), "unit": "GB/s",
-            "per_field_GBps": round(4.0 * nvox / (per_ms * 1e-3) / 1e9, 2), "tuning": tunes}
+            "per_field_GBps": round(4.0 * nvox / (per_ms * 1e-3) / 1e9, 2),
+            "frac_of_peak_budget": round(bud / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "per_field_frac_of_peak_budget": round(bud / (per_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "tuning": tunes}
 
 
 def kernel_rev():
@@ -297,18 +426,36 @@ def regime_stats(qai, field, x32, eb, dev):
             "max_err_over_eb": round(float(err1.abs().max()) / eb, 5)}
 
 
-def cpu_baseline(xq, eb, target_s=15.0):
-    """The CPU oracle, as it stands, on a bounded sample of the same field: a
-    16-plane probe sets a z-slab that takes about target_s; when the whole
-    field takes less, the whole field is run repeatedly for about target_s."""
-    import oracle
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of the calling thread's later parallel
+    regions (the oracle's runtime is libgomp)."""
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
+def _oracle_rate(oracle, xq, eb, target_s):
+    """The oracle on a bounded z-slab of the field sized from a 4-plane probe to
+    take about target_s (the whole field, repeated, when it takes less)."""
     nz = xq.shape[0]
-    oracle.qai(xq[: min(nz, 2)], eb)  # load / build outside the timing
-    probe = xq[: min(nz, 16)]
+    probe = xq[: min(nz, 4)]
     t = time.perf_counter()
     oracle.qai(probe, eb)
     per_plane = (time.perf_counter() - t) / probe.shape[0]
-    planes = int(min(nz, max(16, target_s / max(per_plane, 1e-9))))
+    planes = int(min(nz, max(4, target_s / max(per_plane, 1e-9))))
     slab = xq[:planes]
     reps, dt = 0, 0.0
     while reps == 0 or (planes == nz and dt < target_s and reps < 64):
@@ -316,12 +463,27 @@ def cpu_baseline(xq, eb, target_s=15.0):
         oracle.qai(slab, eb)
         dt += time.perf_counter() - t
         reps += 1
-    gbps = 4.0 * slab.size * reps / dt / 1e9
     what = "the whole field" if planes == nz else f"z-slab {list(slab.shape)} ({planes}/{nz} planes)"
-    return {"value": round(gbps, 5), "unit": "GB/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{what}, {reps} run(s), {slab.size * reps} voxels in total; full Algorithm 4 in FP64 "
-                      f"C/OpenMP with every intermediate kept, {dt:.2f} s",
-            "seconds": round(dt, 3), "mb_per_s": round(gbps * 1e3, 2)}
+    return 4.0 * slab.size * reps / dt / 1e9, dt, f"{what}, {reps} run(s)"
+
+
+def cpu_baseline(xq, eb):
+    """The CPU oracle, as it stands, on bounded samples of the same field: all
+    host threads (about 15 s) and one thread (about 8 s)."""
+    import oracle
+    oracle.qai(xq[: min(xq.shape[0], 2)], eb)  # load / build outside the timing
+    threads = oracle.max_threads()
+    gbps, dt, what = _oracle_rate(oracle, xq, eb, 15.0)
+    one = None
+    if _omp_threads(1):
+        g1, dt1, what1 = _oracle_rate(oracle, xq, eb, 8.0)
+        _omp_threads(threads)
+        one = {"value": round(g1, 6), "unit": "GB/s", "mb_per_s": round(g1 * 1e3, 3), "seconds": round(dt1, 3),
+               "sample": what1}
+    return {"value": round(gbps, 5), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"{what}, full Algorithm 4 in FP64 C/OpenMP with every intermediate kept, {dt:.2f} s",
+            "seconds": round(dt, 3), "mb_per_s": round(gbps * 1e3, 2), "cpu_model": cpu_model(),
+            "one_thread": one, "paper_cpu": PAPER_CPU}
 
 
 if __name__ == "__main__":

@@ -163,9 +163,9 @@ const char* qai_last_error(void);
  * qai_mitigate_ex on it alone. */
 typedef struct qai_batch_plan qai_batch_plan;
 
-/* Plan flag: before capturing, time a small set of launch settings (pass
- * algorithms, seed variant and z-march) on the first field of each distinct
- * shape and use the fastest for every field of that shape. */
+/* Plan flag: every distinct shape runs its autotuned setting (see
+ * qai_autotune): the cached one, or one timed before capture on the first
+ * field of that shape (and then cached). */
 #define QAI_BATCH_AUTOTUNE 0x1u
 
 /* Bytes of device workspace a batch of n fields needs: the sum over fields
@@ -237,6 +237,79 @@ int qai_tuning_get(qai_tuning* t);
 /* Replace the current setting (validated; QAI_EINVAL if out of range).  NULL
  * restores the built-in defaults. */
 int qai_tuning_set(const qai_tuning* t);
+
+/* ------------------------------------------------------------ autotuning
+ * Project addition.  qai_autotune times candidate settings on one field: the
+ * pass algorithms of both EDTs with the seed variants, then, for the fastest,
+ * the line-tile shapes (tile_log2) and workgroup sizes (window_threads) of the
+ * passes it runs as the windowed search.  The winner is stored in a per-shape
+ * cache held by the library; qai_mitigate, qai_mitigate_ex,
+ * qai_mitigate_noalloc and batch plans use a shape's cached setting while the
+ * process-wide setting is the built-in default (never set, or reset with
+ * qai_tuning_set(NULL)).  Results never depend on the setting.
+ *   field, dims, eb  as for qai_mitigate_ex
+ *   ws, ws_bytes     workspace of qai_workspace_bytes(dims), 256-byte aligned
+ *   out              device FP32[N], apart from field (written many times)
+ *   best             receives the chosen setting (nullable)
+ * Synchronises stream (the candidates are timed with HIP events on it). */
+int qai_autotune(const float* field, const int64_t dims[3], float eb, void* ws, size_t ws_bytes, float* out,
+                 void* stream, qai_tuning* best);
+
+/* The cache as a text file: a header line, then one line per shape with
+ * nz ny nx and the fields of qai_tuning in declaration order (force_wide
+ * excluded).  save writes every entry; load validates every line as
+ * qai_tuning_set does and adds (or replaces) the entries; QAI_EINVAL on I/O or
+ * format errors (nothing is added then). */
+int qai_tuning_cache_save(const char* path);
+int qai_tuning_cache_load(const char* path);
+int qai_tuning_cache_clear(void);
+/* Number of shapes in the cache. */
+int qai_tuning_cache_size(void);
+
+/* ------------------------------------------------------------ blocks
+ * The paper's block-decomposed strategies (Section VI-B) on one GPU.  The
+ * field is cut into blocks[0] x blocks[1] x blocks[2] blocks along z, y, x
+ * (extents split as evenly as possible, the first blocks one voxel longer),
+ * each processed as a field of its own:
+ *   QAI_BLOCKS_EP      embarrassingly parallel: each block runs the whole
+ *                      post-pass alone (its faces are domain edges);
+ *   QAI_BLOCKS_APPROX  approximate: each block sees one ghost layer of its
+ *                      neighbours, exchanged twice -- the data for the
+ *                      boundary stencil of step A, then the propagated signs
+ *                      of step B for the sign-flip stencil of step C -- while
+ *                      both EDTs stay local to the block.
+ * The exact strategy is qai_mitigate_ex on the whole field.
+ *   field, dims, eb, params, out, stream  as for qai_mitigate_ex (no taps)
+ *   blocks   host int32[3], each in [1, extent]; at most 4096 blocks
+ *   ws       device workspace of qai_blocks_workspace_bytes, 256-aligned:
+ *            per block a copy of its (ghosted) region, its output and a
+ *            plain workspace; for QAI_BLOCKS_APPROX one word per voxel more
+ * A block grid of 1 x 1 x 1 gives qai_mitigate_ex's result. */
+#define QAI_BLOCKS_EP 0
+#define QAI_BLOCKS_APPROX 1
+size_t qai_blocks_workspace_bytes(const int64_t dims[3], const int32_t blocks[3], int mode);
+int qai_mitigate_blocks(const float* field, const int64_t dims[3], float eb, const qai_params* params,
+                        const int32_t blocks[3], int mode, void* ws, size_t ws_bytes, float* out, void* stream);
+
+/* ------------------------------------------------------------ quality
+ * The paper's quality metrics (Section III-C), comparing an original field
+ * with a decompressed or compensated one on the GPU:
+ *   SSIM (Eq. 3): per window, (2 mu1 mu2 + c1)(2 s12 + c2) /
+ *     ((mu1^2 + mu2^2 + c1)(s1^2 + s2^2 + c2)) with sample means, sample
+ *     variances and covariance (divisor m - 1 for m voxels), c1 = 1e-4,
+ *     c2 = 9e-4, both fields normalised by the original's range; windows of 7
+ *     voxels per axis (the whole extent on an axis shorter than 7) at a stride
+ *     of 2, only whole windows; the result is the mean over windows;
+ *   PSNR (Eq. 4): 20 log10((max - min of the original) / sqrt(MSE)).
+ *   orig, dec  device FP32[N] of the same dims
+ *   ws         device workspace of qai_quality_workspace_bytes(dims), 256-aligned
+ *   result     device double[4] receiving {SSIM, PSNR, MSE, value range of orig};
+ *              SSIM is NaN for a constant original, PSNR +inf for equal fields
+ * QAI_EDIMS when a window would hold fewer than two voxels.  Sums are FP64 in a
+ * fixed order: the result is deterministic. */
+size_t qai_quality_workspace_bytes(const int64_t dims[3]);
+int qai_quality(const float* orig, const float* dec, const int64_t dims[3], void* ws, size_t ws_bytes,
+                double* result, void* stream);
 
 /* ------------------------------------------------------------ utilities */
 

@@ -16,13 +16,15 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _lib
 from ._lib import QAIError, QAI_STATUS_QRANGE  # noqa: F401
 
 __all__ = ["mitigate", "workspace_bytes", "device_status", "backward", "QAIFunction", "fit_params",
-           "BatchPlan", "mitigate_batched", "copy_probe", "profile", "stage_times", "QAIError", "lib"]
+           "BatchPlan", "mitigate_batched", "copy_probe", "profile", "stage_times", "QAIError", "lib", "autotune",
+           "tuning_cache_save", "tuning_cache_load", "tuning_cache_clear", "tuning_cache_size", "quality", "mitigate_blocks"]
 
 
 def lib():
@@ -148,24 +150,43 @@ class QAIFunction(torch.autograd.Function):
         return grad_out, g[0].to(edt), g[1].to(pdt), None
 
 
-def fit_params(x_dec, x_orig, eb, steps=50, eta0=0.9, power0=1.0, lr=0.05, fit_power=True):
+def fit_params(x_dec, x_orig, eb, steps=50, eta0=0.9, power0=1.0, fit_power=True, history=10):
     """Fit eta (and optionally the IDW power) for one field by minimising the
-    MSE between the compensated and the original data with Adam.  Returns
-    ``(eta, power, history_of_mse)``."""
-    eta = torch.tensor(float(eta0), device=x_dec.device, requires_grad=True)
-    pw = torch.tensor(float(power0), device=x_dec.device, requires_grad=fit_power)
-    opt = torch.optim.Adam([eta, pw] if fit_power else [eta], lr=lr)
+    MSE between the compensated and the original data: ``steps`` L-BFGS
+    iterations with a strong-Wolfe line search (the MSE taken relative to its
+    starting value), on float64 parameters (the
+    power as exp(theta), so that every trial value stays positive), each loss
+    evaluation one forward pass and one adjoint on the GPU.  Returns
+    ``(eta, power, history_of_mse)`` (the MSE after each iteration)."""
+    dev = x_dec.device
+    eta = torch.tensor(float(eta0), dtype=torch.float64, device=dev, requires_grad=True)
+    theta = torch.tensor(float(np.log(power0)), dtype=torch.float64, device=dev, requires_grad=fit_power)
+    params = [eta, theta] if fit_power else [eta]
+    # one iteration per step, with up to 25 loss evaluations for its line search
+    opt = torch.optim.LBFGS(params, lr=1.0, max_iter=1, max_eval=25, history_size=history,
+                            line_search_fn="strong_wolfe")
+    xo = x_orig.double()
+
+    def loss_fn():
+        pw = torch.exp(theta)
+        y = QAIFunction.apply(x_dec, eta, pw, eb)
+        return torch.mean((y.double() - xo) ** 2)
+
+    with torch.no_grad():
+        scale = 1.0 / max(float(loss_fn()), 1e-300)  # the optimiser sees the MSE relative to its start
+
+    def closure():
+        opt.zero_grad()
+        loss = loss_fn() * scale
+        loss.backward()
+        return loss
+
     hist = []
     for _ in range(steps):
-        opt.zero_grad()
-        y = QAIFunction.apply(x_dec, eta, pw, eb)
-        loss = torch.mean((y - x_orig) ** 2)
-        loss.backward()
-        opt.step()
+        opt.step(closure)
         with torch.no_grad():
-            pw.clamp_(min=0.05)
-        hist.append(float(loss.detach()))
-    return float(eta.detach()), float(pw.detach()), hist
+            hist.append(float(loss_fn()))
+    return float(eta.detach()), float(torch.exp(theta).detach()), hist
 
 
 class BatchPlan:
@@ -282,6 +303,85 @@ def set_tuning(cfg=None, **kw):
             setattr(t, k, int(v))
     _lib.check(lib().qai_tuning_set(ctypes.byref(t)))
     return get_tuning()
+
+
+def autotune(field, eb, stream=None):
+    """Time the candidate launch settings on ``field`` and cache the fastest
+    for its shape (used by later calls while the process-wide setting is the
+    default); returns the chosen setting as a dict."""
+    L = lib()
+    dims = _check_field(field)
+    ws = new_workspace(field.shape, field.device)
+    out = torch.empty_like(field)
+    t = _lib.Tuning()
+    _lib.check(L.qai_autotune(ctypes.c_void_p(field.data_ptr()), dims, ctypes.c_float(eb),
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()),
+                              _stream_ptr(stream), ctypes.byref(t)))
+    return {k: (list(getattr(t, k)) if hasattr(getattr(t, k), "__len__") else int(getattr(t, k)))
+            for k in TUNING_FIELDS}
+
+
+def tuning_cache_save(path):
+    _lib.check(lib().qai_tuning_cache_save(str(path).encode()))
+
+
+def tuning_cache_load(path):
+    _lib.check(lib().qai_tuning_cache_load(str(path).encode()))
+
+
+def tuning_cache_clear():
+    _lib.check(lib().qai_tuning_cache_clear())
+
+
+def tuning_cache_size():
+    return int(lib().qai_tuning_cache_size())
+
+
+def mitigate_blocks(field, eb, blocks=(2, 2, 2), mode="approximate", eta=0.9, power=1.0, out=None, stream=None):
+    """The post-pass with the field cut into a grid of blocks (the paper's
+    distributed strategies, Section VI-B): ``mode`` "ep" (each block alone) or
+    "approximate" (one-layer exchanges of the data and of the propagated
+    signs, local EDTs).  The exact strategy is ``mitigate`` itself."""
+    L = lib()
+    dims = _check_field(field)
+    if mode not in _lib.BLOCK_MODES:
+        raise ValueError(f"mode must be one of {sorted(_lib.BLOCK_MODES)}")
+    m = _lib.BLOCK_MODES[mode]
+    blk = (ctypes.c_int32 * 3)(*[int(b) for b in ((1,) * (3 - len(blocks)) + tuple(blocks))])
+    nb = int(L.qai_blocks_workspace_bytes(dims, blk, m))
+    if nb == 0:
+        raise QAIError(-1, f"invalid blocks {tuple(blocks)} for shape {tuple(field.shape)}")
+    ws = torch.empty(nb, dtype=torch.uint8, device=field.device)
+    if out is None:
+        out = torch.empty_like(field)
+    prm = _lib.Params(float(eta), float(power), 0)
+    _lib.check(L.qai_mitigate_blocks(ctypes.c_void_p(field.data_ptr()), dims, ctypes.c_float(eb), ctypes.byref(prm),
+                                     blk, m, ctypes.c_void_p(ws.data_ptr()), nb, ctypes.c_void_p(out.data_ptr()),
+                                     _stream_ptr(stream)))
+    return out
+
+
+def quality(orig, dec, stream=None, sync=True):
+    """SSIM (Eq. 3, 7-voxel windows at stride 2) and PSNR (Eq. 4) of ``dec``
+    against ``orig`` on the GPU.  Returns a dict ``{"ssim", "psnr", "mse",
+    "range"}`` (``sync=True``) or the device float64 tensor of those four."""
+    L = lib()
+    dims = _check_field(orig, "orig")
+    _check_field(dec, "dec")
+    if dec.shape != orig.shape:
+        raise ValueError("orig and dec differ in shape")
+    nb = int(L.qai_quality_workspace_bytes(dims))
+    if nb == 0:
+        raise QAIError(-2, f"invalid shape {tuple(orig.shape)}")
+    ws = torch.empty(nb, dtype=torch.uint8, device=orig.device)
+    res = torch.empty(4, dtype=torch.float64, device=orig.device)
+    _lib.check(L.qai_quality(ctypes.c_void_p(orig.data_ptr()), ctypes.c_void_p(dec.data_ptr()), dims,
+                             ctypes.c_void_p(ws.data_ptr()), nb, ctypes.c_void_p(res.data_ptr()),
+                             _stream_ptr(stream)))
+    if not sync:
+        return res
+    v = res.cpu().tolist()
+    return {"ssim": v[0], "psnr": v[1], "mse": v[2], "range": v[3]}
 
 
 def profile(on=True):

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(PKG, "libqai.so")
 
 QAI_OK = 0
 QAI_BATCH_AUTOTUNE = 0x1
+BLOCK_MODES = {"ep": 0, "approximate": 1}
 ERRORS = {-1: "QAI_EINVAL", -2: "QAI_EDIMS", -3: "QAI_ENOWS", -4: "QAI_EHIP", -5: "QAI_ENODEV",
           -6: "QAI_ESTATE"}
 QAI_STATUS_QRANGE = 0x1
@@ -48,7 +49,10 @@ Dims = ctypes.c_int64 * 3
 EXPORTS = ["qai_mitigate", "qai_workspace_bytes", "qai_mitigate_ex", "qai_backward", "qai_device_status",
            "qai_last_error", "qai_batch_workspace_bytes", "qai_batch_plan_create", "qai_batch_plan_launch",
            "qai_batch_plan_launch_per_field", "qai_batch_plan_tuning", "qai_batch_plan_destroy", "qai_copy_probe",
-           "qai_profile_enable", "qai_stage_times", "qai_tuning_get", "qai_tuning_set", "qai_mitigate_noalloc"]
+           "qai_profile_enable", "qai_stage_times", "qai_tuning_get", "qai_tuning_set", "qai_mitigate_noalloc",
+           "qai_autotune", "qai_tuning_cache_save", "qai_tuning_cache_load", "qai_tuning_cache_clear",
+           "qai_tuning_cache_size", "qai_quality_workspace_bytes", "qai_quality", "qai_blocks_workspace_bytes",
+           "qai_mitigate_blocks"]
 
 _lib = None
 
@@ -86,11 +90,23 @@ def load(path=LIB_PATH):
     lib.qai_profile_enable.argtypes = [I]
     lib.qai_tuning_get.argtypes = [ctypes.POINTER(Tuning)]
     lib.qai_tuning_set.argtypes = [ctypes.POINTER(Tuning)]
+    lib.qai_autotune.argtypes = [P, I64P, F, P, SZ, P, P, ctypes.POINTER(Tuning)]
+    lib.qai_tuning_cache_save.argtypes = [ctypes.c_char_p]
+    lib.qai_tuning_cache_load.argtypes = [ctypes.c_char_p]
+    lib.qai_tuning_cache_clear.argtypes = []
+    lib.qai_tuning_cache_size.argtypes = []
+    lib.qai_quality_workspace_bytes.argtypes = [I64P]
+    lib.qai_quality_workspace_bytes.restype = SZ
+    lib.qai_quality.argtypes = [P, P, I64P, P, SZ, P, P]
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    lib.qai_blocks_workspace_bytes.argtypes = [I64P, I32P, I]
+    lib.qai_blocks_workspace_bytes.restype = SZ
+    lib.qai_mitigate_blocks.argtypes = [P, I64P, F, ctypes.POINTER(Params), I32P, I, P, SZ, P, P]
     lib.qai_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_char_p), I,
                                     ctypes.POINTER(I), I]
     for name in EXPORTS:
         if name not in ("qai_workspace_bytes", "qai_last_error", "qai_batch_workspace_bytes",
-                        "qai_batch_plan_destroy"):
+                        "qai_batch_plan_destroy", "qai_quality_workspace_bytes", "qai_blocks_workspace_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -88,6 +88,7 @@ struct StageRec {
 std::mutex g_prof_mu;
 std::mutex g_tune_mu;
 bool g_tune_set = false;
+bool g_tune_user = false; // set by qai_tuning_set with a setting (not NULL)
 qai::Tuning g_tune;
 
 qai::Tuning current_tuning()
@@ -154,6 +155,27 @@ namespace api {
 
 Tuning tuning_now() { return current_tuning(); }
 
+// The setting a plain call on dims runs with: a shape's autotuned entry while
+// the process-wide setting is the built-in default, else that setting.
+Tuning tuning_for(const int64_t dims[3])
+{
+    bool user;
+    Tuning t;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (!g_tune_set) {
+            default_tuning(g_tune);
+            g_tune_set = true;
+        }
+        t = g_tune;
+        user = g_tune_user;
+    }
+    Tuning c;
+    if (!user && cache_lookup(dims, c))
+        return c;
+    return t;
+}
+
 void prof_suppress(bool on) { g_prof_suppress += on ? 1 : -1; }
 
 // k-th region after the header; cap = word_capacity of the field
@@ -171,6 +193,41 @@ void ws_buffers(void* ws, Plan1& p)
     p.bufB = word_buffer(ws, cap, 1);
     p.bufC = word_buffer(ws, cap, 2);
     p.flags = (uint64_t*)word_buffer(ws, cap, 3);
+}
+
+void clear_error() { g_err.clear(); }
+
+int abi_to_tuning(const qai_tuning* in, Tuning& t)
+{
+    default_tuning(t);
+    for (int k = 0; k < 2; ++k) {
+        if (in->edt1_algo[k] < -1 || in->edt1_algo[k] > 4 || in->edt1_algo[k] == 3 || in->edt2_algo[k] < -1 ||
+            in->edt2_algo[k] > 4)
+            return fail(QAI_EINVAL, "algorithm choice: -1 (auto), 0, 1, 2 or 4 for the first EDT, -1..4 for the second");
+        if (in->tile_log2[k] < -1 || in->tile_log2[k] > 6)
+            return fail(QAI_EINVAL, "tile_log2 must be in [-1, 6]");
+    }
+    for (int r : {in->edt1_ring, in->edt2_ring})
+        if (r != 16 && r != 32 && r != 64)
+            return fail(QAI_EINVAL, "ring sizes must be 16, 32 or 64");
+    if (in->seed_rows < -1 || in->seed_rows > 8 || in->seed_planes < 1 || in->seed_planes > 4096)
+        return fail(QAI_EINVAL, "seed_rows must be in [-1, 8] and seed_planes in [1, 4096]");
+    if (in->window_threads < 64 || in->window_threads > 1024 || in->window_threads % 64)
+        return fail(QAI_EINVAL, "window_threads must be a multiple of 64 in [64, 1024]");
+    if (in->force_wide != 0 && in->force_wide != 1)
+        return fail(QAI_EINVAL, "force_wide must be 0 or 1");
+    for (int a = 1; a <= 2; ++a) {
+        t.edt1_algo[a] = in->edt1_algo[a - 1];
+        t.env_algo[a] = in->edt2_algo[a - 1];
+        t.edt1_cap[a] = in->edt1_ring;
+        t.stream_cap[a] = in->edt2_ring;
+        t.env_tx_log2[a] = in->tile_log2[a - 1];
+    }
+    t.seed_ty = in->seed_rows;
+    t.seed_tz = in->seed_planes;
+    t.env_threads = in->window_threads;
+    t.force_wide = in->force_wide;
+    return QAI_OK;
 }
 
 int tuning_to_abi(const Tuning& t, qai_tuning* out)
@@ -242,7 +299,7 @@ int plain_checked(const float* field, const int64_t dims[3], float eb, const qai
     ws_buffers(ws, pl);
     if (taps)
         pl.taps = *taps;
-    const qai::Tuning t = current_tuning();
+    const qai::Tuning t = tuning_for(dims);
     e = qai::run_plain(pl, t, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail_hip(e, "kernel launch");
@@ -450,38 +507,14 @@ int qai_tuning_set(const qai_tuning* in)
     qai::Tuning t;
     qai::default_tuning(t);
     if (in) {
-        for (int k = 0; k < 2; ++k) {
-            if (in->edt1_algo[k] < -1 || in->edt1_algo[k] > 4 || in->edt1_algo[k] == 3 || in->edt2_algo[k] < -1 ||
-                in->edt2_algo[k] > 4)
-                return fail(QAI_EINVAL,
-                            "algorithm choice: -1 (auto), 0, 1, 2 or 4 for the first EDT, -1..4 for the second");
-            if (in->tile_log2[k] < -1 || in->tile_log2[k] > 6)
-                return fail(QAI_EINVAL, "tile_log2 must be in [-1, 6]");
-        }
-        for (int r : {in->edt1_ring, in->edt2_ring})
-            if (r != 16 && r != 32 && r != 64)
-                return fail(QAI_EINVAL, "ring sizes must be 16, 32 or 64");
-        if (in->seed_rows < -1 || in->seed_rows > 8 || in->seed_planes < 1 || in->seed_planes > 4096)
-            return fail(QAI_EINVAL, "seed_rows must be in [-1, 8] and seed_planes in [1, 4096]");
-        if (in->window_threads < 64 || in->window_threads > 1024 || in->window_threads % 64)
-            return fail(QAI_EINVAL, "window_threads must be a multiple of 64 in [64, 1024]");
-        if (in->force_wide != 0 && in->force_wide != 1)
-            return fail(QAI_EINVAL, "force_wide must be 0 or 1");
-        for (int a = 1; a <= 2; ++a) {
-            t.edt1_algo[a] = in->edt1_algo[a - 1];
-            t.env_algo[a] = in->edt2_algo[a - 1];
-            t.edt1_cap[a] = in->edt1_ring;
-            t.stream_cap[a] = in->edt2_ring;
-            t.env_tx_log2[a] = in->tile_log2[a - 1];
-        }
-        t.seed_ty = in->seed_rows;
-        t.seed_tz = in->seed_planes;
-        t.env_threads = in->window_threads;
-        t.force_wide = in->force_wide;
+        const int rc = abi_to_tuning(in, t);
+        if (rc)
+            return rc;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune = t;
     g_tune_set = true;
+    g_tune_user = in != nullptr;
     return QAI_OK;
 }
 

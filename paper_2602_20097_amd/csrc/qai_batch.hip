@@ -5,10 +5,9 @@
 // kernels of different fields can overlap on the GPU.  Every field's result is
 // bit-identical to qai_mitigate_ex on it alone, whatever the branch or tuning.
 //
-// The autotuner (QAI_BATCH_AUTOTUNE) times a small set of launch settings on
-// the first field of each distinct shape and keeps the fastest for every field
-// of that shape.  All settings compute the same transform, so tuning only
-// changes time.
+// With QAI_BATCH_AUTOTUNE every distinct shape runs the autotuner's setting
+// for it (the cached one, or one timed now on the first field of that shape).
+// All settings compute the same transform, so tuning only changes time.
 #include <algorithm>
 #include <map>
 #include <vector>
@@ -59,86 +58,30 @@ void release(qai_batch_plan* p)
     delete p;
 }
 
-// Candidate settings: first-EDT pass, second-EDT pass, seed variant and z-march.
-std::vector<qai::Tuning> candidates(const qai::Tuning& base, int64_t nx)
-{
-    std::vector<qai::Tuning> out;
-    const int e1s[3] = {-1, 4, 1}, e2s[3] = {-1, 3, 1};
-    const int seeds[3][2] = {{0, 16}, {0, 32}, {4, 16}};
-    for (int a : e1s)
-        for (int b : e2s)
-            for (auto& sd : seeds) {
-                if (sd[0] == 0 && nx > 512)
-                    continue; // the register seed variant needs lines of <= 512 voxels
-                qai::Tuning t = base;
-                for (int k = 1; k < 3; ++k) {
-                    t.edt1_algo[k] = a;
-                    t.env_algo[k] = b;
-                }
-                t.seed_ty = sd[0];
-                t.seed_tz = sd[1];
-                out.push_back(t);
-            }
-    return out;
-}
-
-hipError_t time_run(qai::Plan1& pl, const qai::Tuning& t, hipStream_t s, hipEvent_t a, hipEvent_t b, float& ms)
-{
-    hipError_t e = qai::run_plain(pl, t, s); // warm-up
-    if (e != hipSuccess)
-        return e;
-    if ((e = hipEventRecord(a, s)) != hipSuccess)
-        return e;
-    for (int r = 0; r < 2; ++r)
-        if ((e = qai::run_plain(pl, t, s)) != hipSuccess)
-            return e;
-    if ((e = hipEventRecord(b, s)) != hipSuccess)
-        return e;
-    if ((e = hipEventSynchronize(b)) != hipSuccess)
-        return e;
-    return hipEventElapsedTime(&ms, a, b);
-}
-
+// Each distinct shape takes its entry of the tuning cache, or, when it has
+// none, the fastest setting the tuner finds on the first field of that shape
+// (then stored in the cache).
 int autotune(qai_batch_plan* p, const int64_t (*dims)[3], hipStream_t s)
 {
     std::map<std::vector<int64_t>, qai::Tuning> best;
-    hipEvent_t a = nullptr, b = nullptr;
-    hipError_t e = hipEventCreate(&a);
-    if (e == hipSuccess)
-        e = hipEventCreate(&b);
-    if (e != hipSuccess) {
-        if (a)
-            (void)hipEventDestroy(a);
-        return fail_hip(e, "hipEventCreate");
-    }
-    int rc = QAI_OK;
-    for (int i = 0; i < p->n && rc == QAI_OK; ++i) {
+    for (int i = 0; i < p->n; ++i) {
         const std::vector<int64_t> key(dims[i], dims[i] + 3);
         auto it = best.find(key);
         if (it != best.end()) {
             p->tune[i] = it->second;
             continue;
         }
-        float best_ms = 1e30f;
-        qai::Tuning pick = p->tune[i];
-        for (const qai::Tuning& t : candidates(p->tune[i], dims[i][2])) {
-            float ms = 0.0f;
-            e = time_run(p->plans[i], t, s, a, b, ms);
-            if (e != hipSuccess) {
-                rc = fail_hip(e, "autotune run");
-                break;
-            }
-            if (ms < best_ms) {
-                best_ms = ms;
-                pick = t;
-            }
+        qai::Tuning pick;
+        if (!qai::cache_lookup(dims[i], pick)) {
+            const hipError_t e = qai::tune_field(p->plans[i], p->tune[i], s, pick, nullptr);
+            if (e != hipSuccess)
+                return fail_hip(e, "autotune run");
+            qai::cache_store(dims[i], pick);
         }
         best[key] = pick;
         p->tune[i] = pick;
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    return rc;
+    return QAI_OK;
 }
 
 int capture(qai_batch_plan* p)
@@ -234,10 +177,11 @@ int qai_batch_plan_create(int n, const float* const* fields, const int64_t (*dim
         release(p);
         return fail(QAI_ENODEV, "no usable GPU: %s", hipGetErrorString(e));
     }
-    const qai::Tuning base = tuning_now();
     unsigned char* cur = (unsigned char*)ws;
     p->plans.resize(n);
-    p->tune.assign(n, base);
+    p->tune.resize(n);
+    for (int i = 0; i < n; ++i)
+        p->tune[i] = tuning_for(dims[i]);
     for (int i = 0; i < n; ++i) {
         qai::Plan1& pl = p->plans[i];
         pl = qai::Plan1{};

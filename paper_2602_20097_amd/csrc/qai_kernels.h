@@ -101,6 +101,20 @@ struct Tuning {
 
 void default_tuning(Tuning& t);
 
+// The pass algorithm a choice of -1 (automatic) stands for on a field of this
+// shape (axis 1 = y, 2 = z); an explicit choice is returned unchanged.
+int resolve_algo(int want, bool first_edt, int axis, int64_t nz, int64_t ny, int64_t nx);
+
+struct Plan1;
+
+// Per-shape tuning cache (filled by the autotuner, saved to and loaded from a
+// text file).  cache_lookup returns false when the shape has no entry.
+bool cache_lookup(const int64_t dims[3], Tuning& t);
+void cache_store(const int64_t dims[3], const Tuning& t);
+// Time the candidate settings on one field (its plan filled in) and return
+// the fastest; base supplies the fields the candidates do not vary.
+hipError_t tune_field(Plan1& p, const Tuning& base, hipStream_t s, Tuning& best, int* n_timed);
+
 // Host launchers: return hipSuccess or the launch error.
 hipError_t launch_seed(int mode, const SeedArgs& a, hipStream_t s, int ty, int tz);
 hipError_t launch_env(int axis, EnvArgs a, const Tuning& t, hipStream_t s);
@@ -126,6 +140,10 @@ struct Plan1 {
     const uint32_t* w2_final;
 };
 hipError_t run_plain(Plan1& p, const Tuning& t, hipStream_t s);
+// The same in two halves: steps A and B, then (with the first EDT's words in
+// buffer w1, which a caller may edit in between) steps C, D and E.
+hipError_t run_part1(Plan1& p, const Tuning& t, hipStream_t s, int* w1);
+hipError_t run_part2(Plan1& p, const Tuning& t, hipStream_t s, int w1);
 
 // Bytes of the fused final pass's flag words for n voxels: one 64-bit word
 // per 64 voxels, in blocks of 1024 voxels.
@@ -154,6 +172,9 @@ void prof_suppress(bool on);               // pause stage timing on this thread 
 uint32_t* word_buffer(void* ws, int64_t cap, int k); // k-th region, cap = word_capacity
 void ws_buffers(void* ws, Plan1& p); // status word, the three word buffers and the flags (extents set in p)
 int tuning_to_abi(const Tuning& t, qai_tuning* out);
+int abi_to_tuning(const qai_tuning* in, Tuning& t); // validates; QAI_EINVAL with a message
+Tuning tuning_for(const int64_t dims[3]);           // the setting a plain call on dims uses
+void clear_error();
 } // namespace api
 
 } // namespace qai

@@ -2939,7 +2939,7 @@ void final_buffers(int64_t nz, int64_t ny, int64_t nx, int& w1, int& w2)
 // columns and walk the whole column, so they need many column tiles to fill
 // the GPU; a pass with fewer tiles than SIMDs (e.g. the y pass of a 2-D field)
 // takes the windowed search, which is parallel over every voxel.
-static int resolve_algo(int want, bool first_edt, int axis, int64_t nz, int64_t ny, int64_t nx)
+int resolve_algo(int want, bool first_edt, int axis, int64_t nz, int64_t ny, int64_t nx)
 {
     if (want >= 0)
         return want;
@@ -2949,18 +2949,18 @@ static int resolve_algo(int want, bool first_edt, int axis, int64_t nz, int64_t 
     return first_edt ? 4 : 3;
 }
 
-hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
+static Tuning resolved(const Plan1& p, const Tuning& t_in)
 {
     Tuning t = t_in;
     for (int a = 1; a <= 2; ++a) {
         t.edt1_algo[a] = resolve_algo(t_in.edt1_algo[a], true, a, p.nz, p.ny, p.nx);
         t.env_algo[a] = resolve_algo(t_in.env_algo[a], false, a, p.nz, p.ny, p.nx);
     }
-    uint32_t* buf[3] = {p.bufA, p.bufB, p.bufC};
-    prof_begin("clear", s);
-    QAI_TRY(launch_clear(p.status, QAI_HEADER_WORDS, s));
-    prof_end(s);
+    return t;
+}
 
+static SeedArgs seed_args(const Plan1& p)
+{
     SeedArgs sa = {};
     sa.xq = p.xq;
     sa.nx = p.nx;
@@ -2975,6 +2975,20 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
     sa.ts = p.taps.s;
     sa.td1 = p.taps.d1sq;
     sa.tb2 = p.taps.b2;
+    return sa;
+}
+
+// Steps A and B (and the status words): afterwards the first EDT's final
+// words lie in word buffer *w1 (0, 1 or 2).
+hipError_t run_part1(Plan1& p, const Tuning& t_in, hipStream_t s, int* w1)
+{
+    const Tuning t = resolved(p, t_in);
+    uint32_t* buf[3] = {p.bufA, p.bufB, p.bufC};
+    prof_begin("clear", s);
+    QAI_TRY(launch_clear(p.status, QAI_HEADER_WORDS, s));
+    prof_end(s);
+
+    SeedArgs sa = seed_args(p);
 
     // step A + x pass of step B; a 3-D field with both passes of the first
     // EDT on automatic takes them as one search over (y, z) (k_edt1_yz), the
@@ -3036,7 +3050,20 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
         prof_end(s);
         cur ^= 1;
     }
-    const int w1 = cur;
+    *w1 = cur;
+    return hipSuccess;
+}
+
+// Steps C, D and E on the first EDT's words in buffer w1.
+hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
+{
+    const Tuning t = resolved(p, t_in);
+    uint32_t* buf[3] = {p.bufA, p.bufB, p.bufC};
+    SeedArgs sa = seed_args(p);
+    EnvArgs ea = {};
+    ea.nx = p.nx;
+    ea.ny = p.ny;
+    ea.nz = p.nz;
 
     // step C + x pass of step D
     const int o0 = w1 == 0 ? 1 : 0, o1 = w1 == 2 ? 1 : 2;
@@ -3100,6 +3127,13 @@ hipError_t run_plain(Plan1& p, const Tuning& t_in, hipStream_t s)
     p.w1_final = buf[w1];
     p.w2_final = buf[c2];
     return hipSuccess;
+}
+
+hipError_t run_plain(Plan1& p, const Tuning& t, hipStream_t s)
+{
+    int w1 = 0;
+    QAI_TRY(run_part1(p, t, s, &w1));
+    return run_part2(p, t, s, w1);
 }
 
 } // namespace qai

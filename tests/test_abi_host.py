@@ -121,3 +121,34 @@ def test_batch_workspace_and_argument_errors(lib):
     assert h.value is None
     assert lib.qai_batch_plan_launch(None, None) == -6
     assert lib.qai_batch_plan_tuning(None, 0, None) == -1
+
+
+def test_tuning_cache_file_round_trip(lib, tmp_path):
+    """The per-shape tuning cache is host state: load validates every line,
+    save writes back what was loaded, a malformed file adds nothing."""
+    assert lib.qai_tuning_cache_clear() == 0
+    assert lib.qai_tuning_cache_size() == 0
+    good = tmp_path / "cache.txt"
+    rows = ["1 1800 3600 -1 1 -1 1 16 32 5 4 0 16 512", "100 500 500 4 4 3 3 16 32 -1 -1 0 32 256"]
+    good.write_text("qai-tuning-cache 1\n" + "\n".join(rows) + "\n")
+    assert lib.qai_tuning_cache_load(str(good).encode()) == 0
+    assert lib.qai_tuning_cache_size() == 2
+    out = tmp_path / "saved.txt"
+    assert lib.qai_tuning_cache_save(str(out).encode()) == 0
+    lines = out.read_text().splitlines()
+    assert lines[0] == "qai-tuning-cache 1"
+    assert sorted(lines[1:]) == sorted(rows)
+    for bad_row in ("1 1800 3600 -1 1 -1 1 16 33 5 4 0 16 512",   # ring size
+                    "1 1800 3600 -1 1 -1 1 16 32 5 4 0 16 500",   # workgroup size
+                    "0 1800 3600 -1 1 -1 1 16 32 5 4 0 16 512",   # extent
+                    "1 1800 3600 -1 1 -1"):                       # short line
+        bad = tmp_path / "bad.txt"
+        bad.write_text("qai-tuning-cache 1\n64 64 64 -1 -1 -1 -1 16 32 -1 -1 0 16 256\n" + bad_row + "\n")
+        assert lib.qai_tuning_cache_load(str(bad).encode()) == -1, bad_row
+        assert lib.qai_tuning_cache_size() == 2
+    nohdr = tmp_path / "nohdr.txt"
+    nohdr.write_text(rows[0] + "\n")
+    assert lib.qai_tuning_cache_load(str(nohdr).encode()) == -1
+    assert lib.qai_tuning_cache_load(str(tmp_path / "missing.txt").encode()) == -1
+    assert lib.qai_tuning_cache_clear() == 0
+    assert lib.qai_tuning_cache_size() == 0
