@@ -2,6 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--no-cpu-baseline] [--no-regime] [--no-extra]
+                    [--extra quality,blocks,workloads,differentiable,batched]
 
 A step is one full post-pass (Algorithm 4: boundary/sign stencil, two exact
 EDTs, interpolation and compensation) over one synthetic field already
@@ -72,6 +73,7 @@ STAGE_BYTES = {
     "clear": 0,
 }
 
+EXTRAS = ("quality", "blocks", "workloads", "differentiable", "batched")
 EXTRA_WORKLOADS = ["modes256x384x384_eb1e-4", "modes256x384x384_eb1e-3", "modes256x384x384_eb1e-2",
                    "grf2d_1800x3600_k11/3_eb1e-3", "grf256_k3_eb5e-3", "grf64_k3_eb1e-2"]
 
@@ -116,7 +118,13 @@ def main():
     ap.add_argument("--no-regime", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the other workloads, the batch and the adjoint")
+    ap.add_argument("--extra", default=",".join(EXTRAS),
+                    help="comma-separated subset of the parts after the headline: " + ",".join(EXTRAS))
     args = ap.parse_args()
+    extra = set() if args.no_extra else {e for e in args.extra.split(",") if e}
+    unknown = extra - set(EXTRAS)
+    if unknown:
+        ap.error(f"unknown --extra parts {sorted(unknown)}")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(fields would shard by slabs, see the design notes); run with --gpus 1", file=sys.stderr)
@@ -216,22 +224,24 @@ def main():
     }
     if not args.no_regime:
         res["regime"] = regime_stats(qai, field, x32, eb, dev)
-    if not args.no_extra:
+    if "quality" in extra:
         res["quality"] = bench_quality(qai, field, out, x32, dev, max(5, args.steps // 2))
-        if shape[0] > 1:
-            del ws
-            torch.cuda.empty_cache()
-            res["blocks"] = bench_blocks(qai, field, x32, eb, dev, ms_step, max(3, args.steps // 4))
+    if "blocks" in extra and shape[0] > 1:
+        del ws
+        torch.cuda.empty_cache()
+        res["blocks"] = bench_blocks(qai, field, x32, eb, dev, ms_step, max(3, args.steps // 4))
     del field, out
     torch.cuda.empty_cache()
 
-    if not args.no_extra:
+    if "workloads" in extra:
         res["workloads"] = {}
         for name in EXTRA_WORKLOADS:
             res["workloads"][name] = bench_workload(qai, synth, dev, name, max(5, args.steps // 2), args.no_regime)
             torch.cuda.empty_cache()
+    if "differentiable" in extra:
         res["differentiable"] = bench_grad(qai, synth, dev, max(5, args.steps // 2))
         torch.cuda.empty_cache()
+    if "batched" in extra:
         res["batched"] = bench_batched(qai, synth, dev, max(3, args.steps // 4))
         torch.cuda.empty_cache()
 
@@ -388,14 +398,10 @@ def bench_batched(qai, synth, dev, reps):
 
 
 def kernel_rev():
-    """Hash of the kernel sources: traffic counters are only reused while it holds."""
-    import hashlib
-    h = hashlib.sha1()
-    csrc = os.path.join(ROOT, "paper_2602_20097_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:12]
+    """Hash of the plain pass's kernel sources: traffic counters are only
+    reused while it holds."""
+    from paper_2602_20097_amd.profsum import kernel_rev as rev
+    return rev()
 
 
 def regime_stats(qai, field, x32, eb, dev):

@@ -37,10 +37,14 @@ SEED1 = r"k_seed_(lane|seg|slab|xscan|lines)<0"
 SEED2 = r"k_seed_(lane|seg|slab|xscan|lines)<1"
 
 
+# the sources of the plain pass's kernels (the ones the traffic figures cover)
+REV_SOURCES = ("qai_plain.hip", "qai_device.h")
+
+
 def kernel_rev():
     h = hashlib.sha1()
     csrc = os.path.join(ROOT, "paper_2602_20097_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in REV_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
