@@ -208,12 +208,14 @@ typedef struct qai_tuning {
     int32_t edt1_algo[2];  /* y and z passes of the first EDT: 0 streaming envelope, 1 windowed
                               search over LDS tiles, 2 banded envelope over LDS tiles,
                               4 streaming outward search (short distances); -1 (the default)
-                              picks per pass: 1 when the pass has fewer than 1024 tiles of
-                              64 columns, else 4 */
+                              picks per pass: 1 when the pass has fewer than 4096 tiles of
+                              64 columns, else 4; on a 3-D field with both passes at -1 they
+                              run as one search over (y, z) offsets, with the separable passes
+                              (chosen as for -1) behind it where that search does not apply */
     int32_t edt2_algo[2];  /* the same for the second EDT, plus 3: per-lane online envelope
                               (payload-free words; falls back to 0 where its packed ring
                               entries would not fit 32 bits); -1 (the default) picks 1 below
-                              1024 tiles, else 3.  For the z pass of a 3-D call without taps
+                              256 tiles, else 3.  For the z pass of a 3-D call without taps
                               (16-byte aligned field and out), -1 computes the distance to B2
                               only where step E needs it, by an exact outward search along z
                               fused with step E; an explicit choice runs the whole pass */
@@ -290,6 +292,40 @@ int qai_tuning_cache_size(void);
 size_t qai_blocks_workspace_bytes(const int64_t dims[3], const int32_t blocks[3], int mode);
 int qai_mitigate_blocks(const float* field, const int64_t dims[3], float eb, const qai_params* params,
                         const int32_t blocks[3], int mode, void* ws, size_t ws_bytes, float* out, void* stream);
+
+/* ------------------------------------------------------------ coded input
+ * The post-pass straight from coded quantization indices, with no
+ * decompressed copy of the field stored apart from the result.  The code is a
+ * simple one of the paper's kind (Section III-A: the indices are predicted and
+ * encoded losslessly; cuSZp predicts from one prior value with fixed-length
+ * codes): each x-row is cut into segments of 32 voxels (the last one padded
+ * by repeating the row's last index); segment k holds base[k] (its first
+ * index), meta[k] = (first payload word << 8) | b, and its 31 differences to
+ * the prior index, zigzag-coded ((d << 1) ^ (d >> 31)), b bits each (0..32),
+ * packed LSB-first from bit 0 of its payload words.  Segments are numbered
+ * row by row (ceil(nx / 32) per row).  The payload must hold one word more
+ * than the last segment needs.  Offsets are not checked against the payload:
+ * words past its end read as 0 (a malformed code gives wrong values, never a
+ * fault). */
+typedef struct {
+    const int32_t* base;     /* device int32[n_seg] */
+    const uint64_t* meta;    /* device uint64[n_seg] */
+    const uint32_t* payload; /* device uint32[payload_words] */
+    uint64_t payload_words;  /* in [1, 2^29) */
+    int32_t seg_len;         /* 32 */
+} qai_coded;
+
+/* x' = 2 eb q of every voxel (FP32: the exact product rounded once) into the
+ * device FP32[N] array xq. */
+int qai_decode(const qai_coded* code, const int64_t dims[3], float eb, float* xq, void* stream);
+
+/* qai_mitigate_ex from coded indices (no taps): out receives the result; the
+ * first seed pass decodes the indices it reads (lines of up to 512 voxels with
+ * ceil(nx / 64) in {1, 2, 4, 8}; other shapes decode into out first) and writes
+ * x' into out, which the later stages read in place.  ws as for
+ * qai_mitigate_ex; results equal qai_mitigate_ex on the decoded field. */
+int qai_mitigate_coded(const qai_coded* code, const int64_t dims[3], float eb, const qai_params* params, void* ws,
+                       size_t ws_bytes, float* out, void* stream);
 
 /* ------------------------------------------------------------ quality
  * The paper's quality metrics (Section III-C), comparing an original field

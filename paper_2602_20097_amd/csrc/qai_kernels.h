@@ -55,6 +55,13 @@ struct SeedArgs {
     int waves;            // waves per workgroup
     unsigned long long* b1count; // mode 0, k_seed_lane only (nullable): an estimate of the B1 voxels
                                  // (a 1-in-V sample, scaled) is added here
+    // coded indices (k_seed_lane mode 2): segments of 32 voxels per x-row
+    const int32_t* cbase;         // first index of each segment
+    const uint64_t* cmeta;        // (first payload word << 8) | width of its differences
+    const uint32_t* cpay;         // the payload words
+    uint32_t cpay_bytes;          // their size: reads past it return 0 (buffer loads)
+    int64_t segs_row;             // segments per x-row, ceil(nx / 32)
+    float* xout;                  // receives x' = 2 eb q of every voxel
 };
 
 // One lower-envelope pass along y (axis 1) or z (axis 2) over packed words,
@@ -65,7 +72,7 @@ struct EnvArgs {
     int64_t nx, ny, nz;
     int tx_log2;          // columns per tile = 1 << tx_log2
     uint64_t ntiles;
-    const uint32_t* gate; // when set, the pass runs only if *gate != 0 (streaming outward search only)
+    const uint32_t* gate; // when set, the pass runs only if *gate != 0 (windowed and streaming outward searches)
 };
 
 // Words of the workspace header for the fused y/z pass of the first EDT,
@@ -125,7 +132,20 @@ hipError_t launch_clear(uint32_t* p, int n, hipStream_t s);
 // at 2*N words (w1 then w2), status at one word.
 // Word buffers rotate through the passes: A, B and C hold N words each.  On
 // return w1_final / w2_final point at the final words of the two EDTs.
+// Coded quantization indices (qai_coded): segments of 32 voxels per x-row.
+struct Coded {
+    const int32_t* base;
+    const uint64_t* meta;
+    const uint32_t* payload;
+    uint64_t payload_words;
+};
+bool coded_seed_supported(int64_t nx);
+hipError_t launch_seed_coded(const SeedArgs& in, int tz, hipStream_t s);
+// x' = 2 eb q of every voxel from the code (one wave per two segments)
+hipError_t launch_decode(const Coded& c, int64_t nz, int64_t ny, int64_t nx, float two_eb, float* xq, hipStream_t s);
+
 struct Plan1 {
+    const Coded* coded;   // when set, the indices come from this code and x' is written to out
     const float* xq;
     float* out;
     int64_t nz, ny, nx;

@@ -568,6 +568,10 @@ template <int MODE, int V, int WPB, int VW, bool TAPS>
 __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
 {
     static_assert(V % VW == 0, "vector width must divide the voxels per lane");
+    // MODE 0: step A from the decompressed field; 2: step A from coded
+    // indices (decoded here, x' = 2 eb q written to xout); 1: step C
+    constexpr bool SA = MODE != 1, CODED = MODE == 2;
+    static_assert(!CODED || (32 % V == 0 && !TAPS), "coded input: a lane's voxels lie in one 32-voxel segment");
     constexpr int W = V * 64;
     constexpr int R = WPB + 2;
     __shared__ uint32_t rows[2][R * W];
@@ -578,7 +582,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const bool hy = ny > 1, hz = nz > 1, hx = nx > 1;
-    const uint32_t* __restrict__ src = (MODE == 0) ? (const uint32_t*)a.xq : a.w1;
+    const uint32_t* __restrict__ src = (SA) ? (const uint32_t*)a.xq : a.w1;
     const int x0 = V * lane;               // first voxel of the lane
     // stencil range along x: the interior when the axis exists
     const int xmax = hx ? nx - 2 : nx - 1;
@@ -588,7 +592,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
     const uint64_t nblocks = (uint64_t)(A.nby * A.nbz);
     bool bad = false;
     uint32_t nb1 = 0u; // mode 0: B1 among the lanes' first voxels, a 1-in-V sample (wave-uniform)
-    if (MODE == 0 && a.b1count) {
+    if (SA && a.b1count) {
         if (threadIdx.x == 0)
             b1sum = 0ull;
         lds_barrier();
@@ -617,6 +621,47 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
         // copy there waits for the loads: the prefetch would be lost.
         auto load = [&](int64_t zz, int64_t yy, uint32_t (&r)[V]) -> bool {
             const bool ok = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
+            if (CODED) {
+                // the lane's V indices of the line: segment s of the row (the
+                // G = 32 / V lanes of a segment are consecutive), the prediction
+                // from the prior value undone by a prefix sum over the segment
+                constexpr int G = 32 / V;
+                const __amdgpu_buffer_rsrc_t pay = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<uint32_t*>(a.cpay), (short)0, (int)a.cpay_bytes, 0x00020000);
+                const int64_t row = (ok ? zz : 0) * ny + (ok ? yy : 0);
+                const int sg = min(x0 >> 5, (int)a.segs_row - 1);
+                const int64_t ks = row * a.segs_row + sg;
+                const uint64_t mt = a.cmeta[ks];
+                const int bw = (int)(mt & 0xFFu);
+                const uint32_t wo = (uint32_t)(mt >> 8);
+                const uint64_t mask = (bw >= 32) ? 0xFFFFFFFFull : ((1ull << bw) - 1ull);
+                const int p0 = x0 - (sg << 5);
+                int32_t acc = 0;
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const int i = p0 + j;
+                    const uint32_t bit = (uint32_t)(i > 0 ? i - 1 : 0) * (uint32_t)bw;
+                    const uint32_t wd = bw ? (wo + (bit >> 5)) * 4u : 0x80000000u; // width 0: no payload read
+                    const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b32(pay, wd, 0, 0);
+                    const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b32(pay, wd + 4u, 0, 0);
+                    const uint32_t zc = (i > 0) ? (uint32_t)(((((uint64_t)hi << 32) | lo) >> (bit & 31u)) & mask) : 0u;
+                    acc += (int32_t)((zc >> 1) ^ (0u - (zc & 1u)));
+                    r[j] = (uint32_t)acc;
+                }
+                // exclusive scan of the lanes' totals within the segment's lane group
+                int32_t inc = acc;
+#pragma unroll
+                for (int d = 1; d < G; d <<= 1) {
+                    const int32_t t = __shfl_up(inc, d, G);
+                    if ((lane & (G - 1)) >= d)
+                        inc += t;
+                }
+                const int32_t basev = a.cbase[ks] + (inc - acc);
+#pragma unroll
+                for (int j = 0; j < V; ++j)
+                    r[j] = (uint32_t)(basev + (int32_t)r[j]);
+                return ok;
+            }
             const uint32_t* p = src + ((ok ? zz : 0) * ny + (ok ? yy : 0)) * (int64_t)nx;
 #pragma unroll
             for (int j = 0; j < V; j += VW) {
@@ -643,7 +688,11 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
             for (int j = 0; j < V; ++j) {
                 const bool in = ok && x0 + j < nx;
                 const uint32_t w = in ? r[j] : 0u;
-                if (MODE == 0)
+                if (CODED) {
+                    const int32_t qv = (int32_t)w;
+                    bad = bad || qv > (1 << 21) || qv < -(1 << 21);
+                    k[j] = w ^ 0x80000000u;
+                } else if (SA)
                     k[j] = (uint32_t)recover_q(__uint_as_float(w), a.inv2eb, a.two_eb, bad) ^ 0x80000000u;
                 else
                     k[j] = (w & 3u) | (w < 4u ? 4u : 0u);
@@ -705,7 +754,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                     const uint32_t kzp = P2[j], kzm = P0[j];
                     const bool in = line_in && x <= xmax && (j > 0 || first_in);
                     uint32_t code = 0u;
-                    if (MODE == 0) {
+                    if (SA) {
                         // Algorithm 2 (see k_seed_slab): g is the first neighbour that
                         // differs from the voxel, in the order +x, -x, +y, -y, +z, -z
                         uint32_t g = (kxp != kc) ? kxp : kxm;
@@ -735,7 +784,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                         }
                     }
                     sv[j] = ((uint32_t)(x + 4096) << 2) | code;
-                    if (MODE == 0 && j == 0)
+                    if (SA && j == 0)
                         nb1 += (uint32_t)__popcll(__ballot(st[0]));
                 }
                 // nearest site at or before / at or after each voxel among the
@@ -768,11 +817,11 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                     // distances in units of 4 (d4 = 4 d, d4^2 / 4 = d^2 << 2)
                     const uint32_t Lj = max(lv[j], carry_l), Rj = min(rv[j], carry_r);
                     const uint32_t xb4 = (uint32_t)(x0 + j + 4096) << 2;
-                    const uint32_t cm = (MODE == 0) ? ~3u : ~0u; // mode 1 values carry no code
+                    const uint32_t cm = (SA) ? ~3u : ~0u; // mode 1 values carry no code
                     const uint32_t dl4 = xb4 - (Lj & cm), dr4 = (Rj & cm) - xb4;
                     const bool left = dl4 <= dr4;
                     const uint32_t d4 = left ? dl4 : dr4;
-                    const uint32_t cd = (MODE == 0) ? ((left ? Lj : Rj) & 3u) : 0u;
+                    const uint32_t cd = (SA) ? ((left ? Lj : Rj) & 3u) : 0u;
                     word[j] = (__umul24(d4, d4) >> 2) | cd;
                 }
                 if (m == 0ull) {
@@ -791,6 +840,26 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                             *(uint2*)(wrow + j) = make_uint2(word[j], word[j + 1]);
                         else
                             wrow[j] = word[j];
+                    }
+                }
+                if (CODED) {
+                    // the decompressed value of the wave's own line, x' = 2 eb q
+                    // (exact product, one rounding: the decompressor's value)
+                    float* const xrow = a.xout + (z * ny + y) * (int64_t)nx + x0;
+#pragma unroll
+                    for (int j = 0; j < V; j += VW) {
+                        if (x0 + j < nx) {
+                            float xv[VW];
+#pragma unroll
+                            for (int u = 0; u < VW; ++u)
+                                xv[u] = (float)(int32_t)(P1[j + u] ^ 0x80000000u) * a.two_eb;
+                            if (VW == 4)
+                                *(float4*)(xrow + j) = make_float4(xv[0], xv[1], xv[2], xv[3]);
+                            else if (VW == 2)
+                                *(float2*)(xrow + j) = make_float2(xv[0], xv[1]);
+                            else
+                                xrow[j] = xv[0];
+                        }
                     }
                 }
             }
@@ -815,9 +884,9 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
             cur ^= 1;
         }
     }
-    if (MODE == 0 && __ballot(bad) && (threadIdx.x & 63) == 0)
+    if (SA && __ballot(bad) && (threadIdx.x & 63) == 0)
         atomicOr(a.status, QAI_STATUS_QRANGE);
-    if (MODE == 0 && a.b1count) {
+    if (SA && a.b1count) {
         if ((threadIdx.x & 63) == 0)
             atomicAdd(&b1sum, (unsigned long long)nb1 * V);
         lds_barrier();
@@ -1223,6 +1292,8 @@ __global__ __launch_bounds__(1024) void k_env_window(EnvArgs a)
     const int64_t stride = (AXIS == 1) ? a.nx : a.nx * a.ny;
     const int64_t nxb = (a.nx + Tx - 1) >> txl;
     const int total = (int)(n << txl);
+    if (a.gate && *a.gate == 0u)
+        return; // gated pass not needed (uniform over the grid)
 
     for (uint64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
         const uint64_t tl = xcd_remap(t, a.ntiles);
@@ -2444,6 +2515,48 @@ static hipError_t launch_seed_lane(const SeedArgs& in, int tz, hipStream_t s)
     }
 }
 
+// Step A from coded indices (k_seed_lane mode 2): lines of at most 512
+// voxels whose 64 lanes each hold a whole share of one 32-voxel segment.
+bool coded_seed_supported(int64_t nx)
+{
+    const int64_t v = (nx + 63) / 64;
+    return nx <= 512 && (v == 1 || v == 2 || v == 4 || v == 8);
+}
+
+template <int V>
+static hipError_t launch_seed_coded_t(const SeedArgs& in, int tz, hipStream_t s)
+{
+    constexpr int WPB = 8;
+    constexpr int VW4 = (V % 4 == 0) ? 4 : 1, VW2 = (V % 2 == 0) ? 2 : 1;
+    SlabArgs A;
+    A.s = in;
+    A.ty = WPB;
+    A.rows = WPB + 2;
+    A.planes = 3;
+    A.tz = tz;
+    A.nby = (in.ny + WPB - 1) / WPB;
+    A.nbz = (in.nz + tz - 1) / tz;
+    const uint32_t grid = grid_cap((uint64_t)(A.nby * A.nbz), 1u << 20);
+    const uintptr_t al = (uintptr_t)in.xout | (uintptr_t)in.wout;
+    const dim3 g(grid), b(64 * WPB);
+    if (V % 4 == 0 && in.nx % 4 == 0 && al % 16 == 0)
+        return launch_checked(k_seed_lane<2, V, WPB, VW4, false>, g, b, 0, s, A);
+    if (V % 2 == 0 && in.nx % 2 == 0 && al % 8 == 0)
+        return launch_checked(k_seed_lane<2, V, WPB, VW2, false>, g, b, 0, s, A);
+    return launch_checked(k_seed_lane<2, V, WPB, 1, false>, g, b, 0, s, A);
+}
+
+hipError_t launch_seed_coded(const SeedArgs& in, int tz, hipStream_t s)
+{
+    switch ((int)((in.nx + 63) / 64)) {
+    case 1: return launch_seed_coded_t<1>(in, tz, s);
+    case 2: return launch_seed_coded_t<2>(in, tz, s);
+    case 4: return launch_seed_coded_t<4>(in, tz, s);
+    case 8: return launch_seed_coded_t<8>(in, tz, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s, int want_ty, int want_tz)
 {
     if (want_ty < 0)
@@ -2935,18 +3048,25 @@ void final_buffers(int64_t nz, int64_t ny, int64_t nx, int& w1, int& w2)
             return e_;                  \
     } while (0)
 
-// Automatic pass algorithm: the streaming kernels give one wavefront to 64
+// Automatic pass algorithm.  The streaming kernels give one wavefront to 64
 // columns and walk the whole column, so they need many column tiles to fill
-// the GPU; a pass with fewer tiles than SIMDs (e.g. the y pass of a 2-D field)
-// takes the windowed search, which is parallel over every voxel.
+// the GPU; the windowed search is parallel over every voxel but costs the
+// distance it searches.  First EDT (short distances): the windowed search
+// below 4096 tiles (four waves per SIMD; measured: the y and z passes of a
+// sparse-boundary 256^3 field 212 -> 96 us, of 128x128x1024 418 -> 126 us,
+// while 512^3 keeps the streaming search, 563 against 1024 us).  Second EDT
+// (long distances): the per-lane envelope from 256 tiles on (the windowed
+// search took 2.1 ms for the y pass of 100x500x500 and 19 ms at 512^3,
+// the envelope 0.14 / 0.67 ms); the windowed search only for passes with very
+// few tiles, such as the y pass of a 2-D field.
 int resolve_algo(int want, bool first_edt, int axis, int64_t nz, int64_t ny, int64_t nx)
 {
     if (want >= 0)
         return want;
     const int64_t tiles = ((nx + 63) / 64) * (axis == 1 ? nz : ny);
-    if (tiles < 1024)
-        return 1;
-    return first_edt ? 4 : 3;
+    if (first_edt)
+        return tiles < 4096 ? 1 : 4;
+    return tiles < 256 ? 1 : 3;
 }
 
 static Tuning resolved(const Plan1& p, const Tuning& t_in)
@@ -3000,9 +3120,32 @@ hipError_t run_part1(Plan1& p, const Tuning& t_in, hipStream_t s, int* w1)
     sa.b1count = yz ? b1count : nullptr;
     int cur = yz ? 1 : 0;
     sa.wout = buf[cur];
-    prof_begin("seed1_xscan", s);
-    QAI_TRY(launch_seed(0, sa, s, t.seed_ty, t.seed_tz));
-    prof_end(s);
+    if (p.coded && coded_seed_supported(p.nx) && t.seed_ty == 0) {
+        // decode inside the seed pass, which also writes x' into out; the
+        // later stages then take out as their x' (in place)
+        sa.cbase = p.coded->base;
+        sa.cmeta = p.coded->meta;
+        sa.cpay = p.coded->payload;
+        sa.cpay_bytes = (uint32_t)(p.coded->payload_words * 4);
+        sa.segs_row = (p.nx + 31) / 32;
+        sa.xout = p.out;
+        prof_begin("seed1_xscan", s);
+        QAI_TRY(launch_seed_coded(sa, p.nz > 1 ? (t.seed_tz > 0 ? t.seed_tz : 16) : 1, s));
+        prof_end(s);
+        p.xq = p.out;
+    } else {
+        if (p.coded) {
+            // other line shapes: decode x' into out first, then the plain pass in place
+            prof_begin("decode", s);
+            QAI_TRY(launch_decode(*p.coded, p.nz, p.ny, p.nx, 2.0f * p.eb, p.out, s));
+            prof_end(s);
+            p.xq = p.out;
+            sa.xq = p.out;
+        }
+        prof_begin("seed1_xscan", s);
+        QAI_TRY(launch_seed(0, sa, s, t.seed_ty, t.seed_tz));
+        prof_end(s);
+    }
 
     EnvArgs ea = {};
     ea.nx = p.nx;
@@ -3020,9 +3163,11 @@ hipError_t run_part1(Plan1& p, const Tuning& t_in, hipStream_t s, int* w1)
         prof_begin("edt1_yz", s);
         QAI_TRY(launch_edt1_yz(ea, wide, b1count, t.force_wide != 0, s));
         prof_end(s);
-        // the fallback: the streaming outward search, the kernel that reads the gate
+        // the fallback, gated: the separable passes with the automatic choice
+        // for each axis (both candidate kernels read the gate)
         Tuning tf = t1;
-        tf.env_algo[1] = tf.env_algo[2] = 4;
+        tf.env_algo[1] = resolve_algo(-1, true, 1, p.nz, p.ny, p.nx);
+        tf.env_algo[2] = resolve_algo(-1, true, 2, p.nz, p.ny, p.nx);
         ea.gate = wide;
         prof_begin("edt1_fallback", s);
         ea.win = buf[1];
