@@ -24,7 +24,8 @@ from ._lib import QAIError, QAI_STATUS_QRANGE  # noqa: F401
 
 __all__ = ["mitigate", "workspace_bytes", "device_status", "backward", "QAIFunction", "fit_params",
            "BatchPlan", "mitigate_batched", "copy_probe", "profile", "stage_times", "QAIError", "lib", "autotune",
-           "tuning_cache_save", "tuning_cache_load", "tuning_cache_clear", "tuning_cache_size", "quality", "mitigate_blocks"]
+           "tuning_cache_save", "tuning_cache_load", "tuning_cache_clear", "tuning_cache_size", "quality", "mitigate_blocks", "upload_code", "decode",
+           "mitigate_coded"]
 
 
 def lib():
@@ -358,6 +359,51 @@ def mitigate_blocks(field, eb, blocks=(2, 2, 2), mode="approximate", eta=0.9, po
     _lib.check(L.qai_mitigate_blocks(ctypes.c_void_p(field.data_ptr()), dims, ctypes.c_float(eb), ctypes.byref(prm),
                                      blk, m, ctypes.c_void_p(ws.data_ptr()), nb, ctypes.c_void_p(out.data_ptr()),
                                      _stream_ptr(stream)))
+    return out
+
+
+def upload_code(code, device="cuda"):
+    """Device copies of a segment code (the dict of ``synth.encode_indices``):
+    returns a dict of int32 / int64 / int32 tensors plus its shape."""
+    import numpy as _np
+    return {"base": torch.from_numpy(_np.ascontiguousarray(code["base"])).to(device),
+            "meta": torch.from_numpy(_np.ascontiguousarray(code["meta"]).view(_np.int64)).to(device),
+            "payload": torch.from_numpy(_np.ascontiguousarray(code["payload"]).view(_np.int32)).to(device),
+            "seg_len": int(code["seg_len"]), "shape": tuple(code["shape"])}
+
+
+def _coded(dcode):
+    return _lib.Coded(dcode["base"].data_ptr(), dcode["meta"].data_ptr(), dcode["payload"].data_ptr(),
+                      dcode["payload"].numel(), dcode["seg_len"])
+
+
+def decode(dcode, eb, out=None, stream=None):
+    """x' = 2 eb q from a device segment code (``upload_code``)."""
+    shape = dcode["shape"]
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=dcode["base"].device)
+    c = _coded(dcode)
+    _lib.check(lib().qai_decode(ctypes.byref(c), _lib.dims3(shape), ctypes.c_float(eb),
+                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def mitigate_coded(dcode, eb, eta=0.9, power=1.0, out=None, workspace=None, stream=None):
+    """The post-pass from a device segment code (``upload_code``): the first
+    seed pass decodes the indices and writes x' into ``out``, which the later
+    stages read in place; returns ``out``."""
+    L = lib()
+    shape = dcode["shape"]
+    dev = dcode["base"].device
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = new_workspace(shape, dev)
+    c = _coded(dcode)
+    prm = _lib.Params(float(eta), float(power), 0)
+    _lib.check(L.qai_mitigate_coded(ctypes.byref(c), _lib.dims3(shape), ctypes.c_float(eb), ctypes.byref(prm),
+                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 

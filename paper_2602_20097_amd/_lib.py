@@ -44,6 +44,11 @@ class Tuning(ctypes.Structure):
                 ("seed_planes", ctypes.c_int32), ("window_threads", ctypes.c_int32), ("force_wide", ctypes.c_int32)]
 
 
+class Coded(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_void_p), ("meta", ctypes.c_void_p), ("payload", ctypes.c_void_p),
+                ("payload_words", ctypes.c_uint64), ("seg_len", ctypes.c_int32)]
+
+
 Dims = ctypes.c_int64 * 3
 
 EXPORTS = ["qai_mitigate", "qai_workspace_bytes", "qai_mitigate_ex", "qai_backward", "qai_device_status",
@@ -52,7 +57,7 @@ EXPORTS = ["qai_mitigate", "qai_workspace_bytes", "qai_mitigate_ex", "qai_backwa
            "qai_profile_enable", "qai_stage_times", "qai_tuning_get", "qai_tuning_set", "qai_mitigate_noalloc",
            "qai_autotune", "qai_tuning_cache_save", "qai_tuning_cache_load", "qai_tuning_cache_clear",
            "qai_tuning_cache_size", "qai_quality_workspace_bytes", "qai_quality", "qai_blocks_workspace_bytes",
-           "qai_mitigate_blocks"]
+           "qai_mitigate_blocks", "qai_decode", "qai_mitigate_coded"]
 
 _lib = None
 
@@ -102,6 +107,8 @@ def load(path=LIB_PATH):
     lib.qai_blocks_workspace_bytes.argtypes = [I64P, I32P, I]
     lib.qai_blocks_workspace_bytes.restype = SZ
     lib.qai_mitigate_blocks.argtypes = [P, I64P, F, ctypes.POINTER(Params), I32P, I, P, SZ, P, P]
+    lib.qai_decode.argtypes = [ctypes.POINTER(Coded), I64P, F, P, P]
+    lib.qai_mitigate_coded.argtypes = [ctypes.POINTER(Coded), I64P, F, ctypes.POINTER(Params), P, SZ, P, P]
     lib.qai_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_char_p), I,
                                     ctypes.POINTER(I), I]
     for name in EXPORTS:

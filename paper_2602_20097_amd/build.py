@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libqai.so")
 
-SOURCES = ["qai_plain.hip", "qai_grad.hip", "qai_batch.hip", "qai_tune.hip", "qai_quality.hip", "qai_blocks.hip", "qai_api.hip"]
+SOURCES = ["qai_plain.hip", "qai_grad.hip", "qai_batch.hip", "qai_tune.hip", "qai_quality.hip", "qai_blocks.hip", "qai_codec.hip", "qai_api.hip"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

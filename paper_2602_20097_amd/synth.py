@@ -125,7 +125,9 @@ def quantize(x, rel_eb):
     if np.abs(q64).max() > 2 ** 21:
         raise ValueError("quantization index exceeds 2^21")
     q = q64.astype(np.int32)
-    xq = (2.0 * eb * q64).astype(np.float32)
+    # decompression from the integer index (a zero index gives +0, as any
+    # decoder of the indices does; the FP64 product is exact, rounded once)
+    xq = (2.0 * eb * q.astype(np.float64)).astype(np.float32)
     return x32, xq, q, eb
 
 
@@ -169,3 +171,61 @@ def batch_specs(seed=SEED_BASE + 5):
 def make_batch_field(spec):
     x = grf(spec["shape"], spec["beta"], spec["seed"])
     return quantize(x, spec["rel"])
+
+
+# ------------------------------------------------------------- coded indices
+# A simple pre-quantization code of the index array (the paper's Section
+# III-A: the indices are predicted and encoded losslessly; its cuSZp
+# comparison predicts from one prior value and uses fixed-length codes).
+# Each x-row is cut into segments of SEG = 32 voxels (the last one padded by
+# repeating the row's last value).  A segment stores its first index (base),
+# the width b (0..32 bits) of its 31 zigzag-coded differences to the prior
+# value, and those differences packed LSB-first from bit 0 of its own run of
+# 32-bit payload words; meta = (first payload word << 8) | b.  The payload
+# ends with one spare zero word, so a decoder may read two words from any
+# difference's first word.  This module only produces code from indices; it
+# decodes nothing.
+SEG = 32
+
+
+def encode_indices(q):
+    """Encode an int32 index array ``(nz, ny, nx)``: returns a dict with
+    ``base`` (int32[n_seg]), ``meta`` (uint64[n_seg]), ``payload``
+    (uint32[words + 1]), ``seg_len`` and the compressed size in bytes."""
+    q = np.asarray(q, dtype=np.int64)
+    if q.ndim != 3:
+        q = q.reshape((1,) * (3 - q.ndim) + q.shape)
+    nz, ny, nx = q.shape
+    s_row = -(-nx // SEG)
+    rows = q.reshape(-1, nx)
+    pad = s_row * SEG - nx
+    if pad:
+        rows = np.concatenate([rows, np.repeat(rows[:, -1:], pad, axis=1)], axis=1)
+    seg = rows.reshape(-1, SEG)
+    base = seg[:, 0].astype(np.int32)
+    r = np.diff(seg, axis=1)                                  # 31 differences to the prior value
+    z = ((r << 1) ^ (r >> 63)).astype(np.uint64)              # zigzag: small magnitudes, small codes
+    zmax = z.max(axis=1)
+    b = np.zeros(len(seg), np.int64)
+    nzm = zmax > 0
+    b[nzm] = np.floor(np.log2(zmax[nzm].astype(np.float64))).astype(np.int64) + 1
+    # guard the float log at powers of two
+    b[nzm] += (zmax[nzm] >> b[nzm].astype(np.uint64)) > 0
+    b[nzm] -= (zmax[nzm] >> (b[nzm] - 1).astype(np.uint64)) == 0
+    words = (31 * b + 31) // 32
+    off = np.zeros(len(seg), np.int64)
+    off[1:] = np.cumsum(words)[:-1]
+    total = int(words.sum())
+    payload = np.zeros(total + 1, np.uint32)
+    for width in np.unique(b[b > 0]):
+        idx = np.nonzero(b == width)[0]
+        bits = ((z[idx][:, :, None] >> np.arange(width, dtype=np.uint64)) & 1).astype(np.uint8)
+        bits = bits.reshape(len(idx), 31 * width)
+        nw = (31 * width + 31) // 32
+        bits = np.concatenate([bits, np.zeros((len(idx), nw * 32 - 31 * width), np.uint8)], axis=1)
+        packed = np.packbits(bits.reshape(len(idx), nw, 32), axis=2, bitorder="little")
+        wv = packed.view("<u4").reshape(len(idx), nw)
+        payload[(off[idx][:, None] + np.arange(nw)).ravel()] = wv.ravel()
+    meta = ((off.astype(np.uint64) << np.uint64(8)) | b.astype(np.uint64)).astype(np.uint64)
+    nbytes = base.nbytes + meta.nbytes + payload.nbytes
+    return dict(base=base, meta=meta, payload=payload, seg_len=SEG, shape=(nz, ny, nx), nbytes=nbytes)

@@ -152,3 +152,18 @@ def test_tuning_cache_file_round_trip(lib, tmp_path):
     assert lib.qai_tuning_cache_load(str(tmp_path / "missing.txt").encode()) == -1
     assert lib.qai_tuning_cache_clear() == 0
     assert lib.qai_tuning_cache_size() == 0
+
+
+def test_coded_argument_errors(lib):
+    base = ctypes.c_void_p(0x1000)
+    c = _lib.Coded(0x1000, 0x2000, 0x3000, 10, 32)
+    d = _lib.Dims(4, 4, 40)
+    assert lib.qai_mitigate_coded(None, d, ctypes.c_float(0.1), None, FAKE, 1 << 30, FAKE, None) == -1
+    bad = _lib.Coded(0x1000, 0x2000, 0x3000, 10, 16)
+    assert lib.qai_mitigate_coded(ctypes.byref(bad), d, ctypes.c_float(0.1), None, FAKE, 1 << 30, FAKE, None) == -1
+    assert "32" in lib.qai_last_error().decode()
+    empty = _lib.Coded(0x1000, 0x2000, 0x3000, 0, 32)
+    assert lib.qai_decode(ctypes.byref(empty), d, ctypes.c_float(0.1), FAKE, None) == -1
+    assert lib.qai_decode(ctypes.byref(c), _lib.Dims(0, 4, 4), ctypes.c_float(0.1), FAKE, None) == -2
+    assert lib.qai_mitigate_coded(ctypes.byref(c), d, ctypes.c_float(0.1), None, FAKE, 10, FAKE, None) == -3
+    del base
