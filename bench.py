@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--no-cpu-baseline] [--no-regime] [--no-extra]
-                    [--extra quality,blocks,workloads,differentiable,batched]
+                    [--extra quality,blocks,coded,workloads,differentiable,batched]
 
 A step is one full post-pass (Algorithm 4: boundary/sign stencil, two exact
 EDTs, interpolation and compensation) over one synthetic field already
@@ -22,12 +22,15 @@ Prints ONE JSON line on stdout (everything else goes to stderr):
   while the kernels are the ones measured) and against a copy kernel;
 * workloads = the other configurations of the metric (the 256x384x384 field at
   three bounds, the 2-D 1800x3600 field, the 256^3 field of the
-  differentiable form with its adjoint, the 64^3 field), each with its regime;
+  differentiable form with its adjoint, the 64^3 field), each with its regime,
+  timed with the autotuner's setting for its shape (and with the default);
 * quality = SSIM and PSNR on the GPU before and after the pass (also per
   workload: the eb-distortion sweep of the 256x384x384 field), and the metric
   kernels' rate;
 * blocks = the paper's block strategies (embarrassingly parallel, approximate)
   on 2 x 2 x 2 blocks beside the exact pass: time and quality;
+* coded = the pass from coded indices (decoded inside the first seed pass)
+  against decoding first, with the code's bytes per voxel;
 * batched = the 48-field uneven batch, one graph launch vs per-field launches;
 * cpu_baseline = the CPU oracle on the host's cores and on one core.
 """
@@ -73,7 +76,7 @@ STAGE_BYTES = {
     "clear": 0,
 }
 
-EXTRAS = ("quality", "blocks", "workloads", "differentiable", "batched")
+EXTRAS = ("quality", "blocks", "coded", "workloads", "differentiable", "batched")
 EXTRA_WORKLOADS = ["modes256x384x384_eb1e-4", "modes256x384x384_eb1e-3", "modes256x384x384_eb1e-2",
                    "grf2d_1800x3600_k11/3_eb1e-3", "grf256_k3_eb5e-3", "grf64_k3_eb1e-2"]
 
@@ -230,6 +233,8 @@ def main():
         del ws
         torch.cuda.empty_cache()
         res["blocks"] = bench_blocks(qai, field, x32, eb, dev, ms_step, max(3, args.steps // 4))
+    if "coded" in extra:
+        res["coded"] = bench_coded(qai, synth, q, eb, field, dev, ms_step, max(5, args.steps // 2))
     del field, out
     torch.cuda.empty_cache()
 
@@ -316,7 +321,40 @@ def bench_blocks(qai, field, x32, eb, dev, exact_ms, reps, blocks=(2, 2, 2)):
     return res
 
 
+def bench_coded(qai, synth, q, eb, field, dev, plain_ms, reps):
+    """The post-pass from coded indices (segment code, decoded inside the first
+    seed pass) against decoding to x' first and running the plain pass; the
+    bytes of the code per voxel beside the 4 of x'."""
+    import torch
+    t0 = time.time()
+    code = synth.encode_indices(q)
+    dc = qai.upload_code(code, dev)
+    n = int(q.size)
+    log(f"coded: {code['nbytes'] / n:.3f} B/voxel of code, encoded in {time.time() - t0:.1f}s")
+    out = torch.empty_like(field)
+    xd = torch.empty_like(field)
+    ws = qai.new_workspace(field.shape, dev)
+    s = torch.cuda.current_stream()
+    f_el, _ = timed_steps(lambda: qai.mitigate_coded(dc, eb, out=out, workspace=ws), reps, 2, s)
+    ok = bool(torch.equal(out.view(torch.int32), qai.mitigate(field, eb).view(torch.int32)))
+
+    def unfused():
+        qai.decode(dc, eb, out=xd)
+        qai.mitigate(xd, eb, out=out, workspace=ws)
+    u_el, _ = timed_steps(unfused, reps, 2, s)
+    d_el, _ = timed_steps(lambda: qai.decode(dc, eb, out=xd), reps, 2, s)
+    fused_ms, unf_ms, dec_ms = f_el * 1e3 / reps, u_el * 1e3 / reps, d_el * 1e3 / reps
+    log(f"coded: fused {fused_ms:.3f} ms, decode + plain {unf_ms:.3f} ms (decode {dec_ms:.3f} ms); "
+        f"plain on x' {plain_ms:.3f} ms; equal to the plain pass: {ok}")
+    return {"code_bytes_per_voxel": round(code["nbytes"] / n, 4), "fused_ms": round(fused_ms, 4),
+            "decode_then_plain_ms": round(unf_ms, 4), "decode_ms": round(dec_ms, 4),
+            "plain_ms": round(plain_ms, 4), "fused_GBps": round(4.0 * n / (fused_ms * 1e-3) / 1e9, 2),
+            "equal_to_plain": ok}
+
+
 def bench_workload(qai, synth, dev, name, steps, no_regime):
+    """One of the metric's other configurations: the default setting, then the
+    autotuner's setting for the shape (cached, used by the same call)."""
     import torch
     x32, xq, q, eb = synth.make_workload(name)
     n = int(np.prod(xq.shape))
@@ -324,14 +362,19 @@ def bench_workload(qai, synth, dev, name, steps, no_regime):
     out = torch.empty_like(t)
     ws = qai.new_workspace(t.shape, dev)
     s = torch.cuda.current_stream()
-    elapsed, step = timed_steps(lambda: qai.mitigate(t, eb, out=out, workspace=ws), steps, 3, s)
+    run = lambda: qai.mitigate(t, eb, out=out, workspace=ws)  # noqa: E731
+    el_def, _ = timed_steps(run, steps, 3, s)
+    tuned = qai.autotune(t, eb)
+    elapsed, step = timed_steps(run, steps, 3, s)
+    qai.tuning_cache_clear()
     ms = elapsed * 1e3 / steps
     bud = budget(xq.shape) * n
     entry = {"shape": list(xq.shape), "voxels": n, "eb": eb, "ms": round(ms, 4),
              "device_ms_median": round(step["median"], 4),
              "GBps": round(4.0 * n / (ms * 1e-3) / 1e9, 2),
              "budget_bytes_per_voxel": budget(xq.shape),
-             "frac_of_peak_budget": round(bud / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+             "frac_of_peak_budget": round(bud / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+             "default_setting_ms": round(el_def * 1e3 / steps, 4), "tuned": tuned}
     if not no_regime:
         entry["regime"] = regime_stats(qai, t, x32, eb, dev)
     if min(xq.shape[1:]) >= 2:
@@ -377,7 +420,9 @@ def bench_batched(qai, synth, dev, reps):
         ebs.append(eb)
     nvox = sum(int(f.numel()) for f in fields)
     log(f"batch of {len(fields)} fields, {nvox} voxels, generated in {time.time() - t0:.1f}s")
-    plan = qai.BatchPlan(fields, ebs, autotune=True)
+    t1 = time.time()
+    plan = qai.BatchPlan(fields, ebs, autotune=True, tune_each=True)
+    log(f"batch plan (autotuned per shape, pass choice per field) in {time.time() - t1:.1f}s")
     s = torch.cuda.current_stream()
     g_el, gstep = timed_steps(plan.launch, reps, 1, s)
     p_el, _ = timed_steps(plan.launch_per_field, reps, 1, s)

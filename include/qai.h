@@ -167,6 +167,11 @@ typedef struct qai_batch_plan qai_batch_plan;
  * qai_autotune): the cached one, or one timed before capture on the first
  * field of that shape (and then cached). */
 #define QAI_BATCH_AUTOTUNE 0x1u
+/* Plan flag (implies QAI_BATCH_AUTOTUNE): each field then also times the
+ * pass-algorithm variants of its shape's setting (first and second EDT:
+ * automatic, envelope, windowed) on itself and keeps the fastest, since the
+ * best pass choice follows a field's boundary density more than its shape. */
+#define QAI_BATCH_TUNE_EACH 0x2u
 
 /* Bytes of device workspace a batch of n fields needs: the sum over fields
  * of qai_workspace_bytes, each rounded up to 256.  0 for invalid input. */
@@ -177,7 +182,7 @@ size_t qai_batch_workspace_bytes(int n, const int64_t (*dims)[3]);
  *                 its input)
  *   dims, ebs     n host triples {nz, ny, nx} and n host error bounds
  *   params        shared step-E parameters (NULL = defaults)
- *   flags         0 or QAI_BATCH_AUTOTUNE (autotuning runs the pipeline on
+ *   flags         0, QAI_BATCH_AUTOTUNE or QAI_BATCH_TUNE_EACH (autotuning runs the pipeline on
  *                 the first field of each shape, writing its output)
  *   ws, ws_bytes  device workspace of qai_batch_workspace_bytes, 256-aligned
  *   stream        stream for the autotuning runs; synchronised before capture

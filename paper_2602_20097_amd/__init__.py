@@ -194,10 +194,13 @@ class BatchPlan:
     """Batched form: many float32 CUDA fields of uneven shapes run by one
     hipGraph launch (``qai_batch_plan_*``).  ``outs`` and the workspace are
     allocated here unless given; the plan keeps references to every tensor it
-    uses.  ``autotune=True`` times a few launch settings on the first field of
-    each distinct shape before capture (results are unchanged by it)."""
+    uses.  ``autotune=True`` takes the autotuner's setting for each distinct
+    shape (timed on its first field unless cached); ``tune_each=True`` also
+    times the pass-algorithm variants on every field (results are unchanged by
+    either)."""
 
-    def __init__(self, fields, ebs, outs=None, eta=0.9, power=1.0, autotune=True, workspace=None, stream=None):
+    def __init__(self, fields, ebs, outs=None, eta=0.9, power=1.0, autotune=True, workspace=None, stream=None,
+                 tune_each=False):
         L = lib()
         if len(fields) != len(ebs) or not fields:
             raise ValueError("one error bound per field, at least one field")
@@ -218,7 +221,8 @@ class BatchPlan:
         prm = _lib.Params(float(eta), float(power), 0)
         h = ctypes.c_void_p()
         _lib.check(L.qai_batch_plan_create(n, fp, dims, eb, op, ctypes.byref(prm),
-                                           _lib.QAI_BATCH_AUTOTUNE if autotune else 0,
+                                           (_lib.QAI_BATCH_AUTOTUNE | (_lib.QAI_BATCH_TUNE_EACH if tune_each else 0))
+                                           if autotune else 0,
                                            ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                            _stream_ptr(stream), ctypes.byref(h)))
         self._h = h

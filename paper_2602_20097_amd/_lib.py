@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(PKG, "libqai.so")
 
 QAI_OK = 0
 QAI_BATCH_AUTOTUNE = 0x1
+QAI_BATCH_TUNE_EACH = 0x2
 BLOCK_MODES = {"ep": 0, "approximate": 1}
 ERRORS = {-1: "QAI_EINVAL", -2: "QAI_EDIMS", -3: "QAI_ENOWS", -4: "QAI_EHIP", -5: "QAI_ENODEV",
           -6: "QAI_ESTATE"}

@@ -61,7 +61,7 @@ void release(qai_batch_plan* p)
 // Each distinct shape takes its entry of the tuning cache, or, when it has
 // none, the fastest setting the tuner finds on the first field of that shape
 // (then stored in the cache).
-int autotune(qai_batch_plan* p, const int64_t (*dims)[3], hipStream_t s)
+int autotune(qai_batch_plan* p, const int64_t (*dims)[3], hipStream_t s, bool each)
 {
     std::map<std::vector<int64_t>, qai::Tuning> best;
     for (int i = 0; i < p->n; ++i) {
@@ -80,6 +80,16 @@ int autotune(qai_batch_plan* p, const int64_t (*dims)[3], hipStream_t s)
         }
         best[key] = pick;
         p->tune[i] = pick;
+    }
+    if (each) {
+        // every field: the pass-algorithm variants of its shape's setting
+        for (int i = 0; i < p->n; ++i) {
+            qai::Tuning pick;
+            const hipError_t e = qai::refine_field(p->plans[i], p->tune[i], s, pick);
+            if (e != hipSuccess)
+                return fail_hip(e, "autotune run");
+            p->tune[i] = pick;
+        }
     }
     return QAI_OK;
 }
@@ -146,7 +156,7 @@ int qai_batch_plan_create(int n, const float* const* fields, const int64_t (*dim
     *plan = nullptr;
     if (n < 1 || !fields || !dims || !ebs || !outs)
         return fail(QAI_EINVAL, "a batch needs n >= 1 fields, dims, bounds and outputs");
-    if (flags & ~(uint32_t)QAI_BATCH_AUTOTUNE)
+    if (flags & ~(uint32_t)(QAI_BATCH_AUTOTUNE | QAI_BATCH_TUNE_EACH))
         return fail(QAI_EINVAL, "unknown batch flags 0x%x", flags);
     qai_params prm;
     int rc = check_params(params, &prm);
@@ -217,9 +227,9 @@ int qai_batch_plan_create(int n, const float* const* fields, const int64_t (*dim
         release(p);
         return fail_hip(e, "batch streams");
     }
-    if (flags & QAI_BATCH_AUTOTUNE) {
+    if (flags & (QAI_BATCH_AUTOTUNE | QAI_BATCH_TUNE_EACH)) {
         prof_suppress(true);
-        rc = autotune(p, dims, (hipStream_t)stream);
+        rc = autotune(p, dims, (hipStream_t)stream, (flags & QAI_BATCH_TUNE_EACH) != 0);
         prof_suppress(false);
         if (rc) {
             release(p);

@@ -11,6 +11,7 @@
 // ever stored apart from the result.  Lines whose lanes would straddle
 // segments take a separate decode (k_decode) into out first.
 #include "qai.h"
+#include "qai_code.h"
 #include "qai_device.h"
 #include "qai_kernels.h"
 
@@ -19,38 +20,36 @@ using namespace qai::api;
 namespace qai {
 namespace {
 
-// Two segments per wave: lane i of each half takes position i of its
-// segment, the differences are summed by a 32-lane inclusive scan.
+// Sixteen segments per wave: four lanes per segment, eight voxels per lane
+// (decode_share), written as two 16-byte stores where the row allows.
 __global__ __launch_bounds__(256) void k_decode(const int32_t* __restrict__ base, const uint64_t* __restrict__ meta,
                                                 const uint32_t* __restrict__ pay, uint32_t pay_bytes, int64_t nrows,
                                                 int64_t nx, int64_t segs_row, float two_eb, float* __restrict__ xq)
 {
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(pay), (short)0, (int)pay_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = payload_rsrc(pay, pay_bytes);
     const int64_t nseg = nrows * segs_row;
-    const int i = threadIdx.x & 31;
-    for (int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5; k < nseg;
-         k += ((int64_t)gridDim.x * blockDim.x) >> 5) {
-        const uint64_t mt = meta[k];
-        const int bw = (int)(mt & 0xFFu);
-        const uint32_t wo = (uint32_t)(mt >> 8);
-        const uint64_t mask = (bw >= 32) ? 0xFFFFFFFFull : ((1ull << bw) - 1ull);
-        const uint32_t bit = (uint32_t)(i > 0 ? i - 1 : 0) * (uint32_t)bw;
-        const uint32_t wd = bw ? (wo + (bit >> 5)) * 4u : 0x80000000u;
-        const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b32(rs, wd, 0, 0);
-        const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b32(rs, wd + 4u, 0, 0);
-        const uint32_t zc = (i > 0) ? (uint32_t)(((((uint64_t)hi << 32) | lo) >> (bit & 31u)) & mask) : 0u;
-        int32_t v = (int32_t)((zc >> 1) ^ (0u - (zc & 1u)));
-#pragma unroll
-        for (int d = 1; d < 32; d <<= 1) {
-            const int32_t t = __shfl_up(v, d, 32);
-            if (i >= d)
-                v += t;
-        }
+    const int lane = threadIdx.x & 63;
+    const int part = lane & 3;
+    const int64_t groups = (nseg + 15) / 16; // 16 segments per wave
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < groups; w += nwaves) {
+        const int64_t k = min(w * 16 + (lane >> 2), nseg - 1); // the last wave repeats the last segment
+        int32_t q[8];
+        decode_share<8>(base, meta, rs, k, part * 8, lane, q);
         const int64_t row = k / segs_row, sg = k - row * segs_row;
-        const int64_t x = sg * 32 + i;
-        if (x < nx)
-            xq[row * nx + x] = (float)(base[k] + v) * two_eb;
+        const int64_t x = sg * 32 + part * 8;
+        float* const dst = xq + row * nx + x;
+        if (x + 8 <= nx && ((row * nx + x) & 3) == 0 && (((uintptr_t)xq) & 15) == 0) {
+            *reinterpret_cast<float4*>(dst) =
+                make_float4((float)q[0] * two_eb, (float)q[1] * two_eb, (float)q[2] * two_eb, (float)q[3] * two_eb);
+            *reinterpret_cast<float4*>(dst + 4) =
+                make_float4((float)q[4] * two_eb, (float)q[5] * two_eb, (float)q[6] * two_eb, (float)q[7] * two_eb);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (x + j < nx)
+                    dst[j] = (float)q[j] * two_eb;
+        }
     }
 }
 
@@ -71,7 +70,7 @@ int check_code(const qai_coded* c, const int64_t dims[3])
 hipError_t launch_decode(const Coded& c, int64_t nz, int64_t ny, int64_t nx, float two_eb, float* xq, hipStream_t s)
 {
     const int64_t segs_row = (nx + 31) / 32, nseg = nz * ny * segs_row;
-    const int64_t blocks = (nseg + 7) / 8;
+    const int64_t blocks = (nseg + 63) / 64; // 4 waves of 16 segments
     return launch_checked(k_decode, dim3((uint32_t)(blocks < (1 << 20) ? blocks : (1 << 20))), dim3(256), 0, s,
                           c.base, c.meta, c.payload, (uint32_t)(c.payload_words * 4), nz * ny, nx, segs_row, two_eb,
                           xq);

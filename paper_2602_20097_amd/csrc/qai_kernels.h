@@ -121,6 +121,9 @@ void cache_store(const int64_t dims[3], const Tuning& t);
 // Time the candidate settings on one field (its plan filled in) and return
 // the fastest; base supplies the fields the candidates do not vary.
 hipError_t tune_field(Plan1& p, const Tuning& base, hipStream_t s, Tuning& best, int* n_timed);
+// Time the pass-algorithm variants of a shape's setting on one field (boundary
+// density decides between them more than shape) and return the fastest.
+hipError_t refine_field(Plan1& p, const Tuning& shape_best, hipStream_t s, Tuning& best);
 
 // Host launchers: return hipSuccess or the launch error.
 hipError_t launch_seed(int mode, const SeedArgs& a, hipStream_t s, int ty, int tz);

@@ -17,6 +17,7 @@
 // No dense contraction exists on this path: the stencil and scan kernels are
 // bound by VALU issue, the envelope and search kernels by dependent latency,
 // the streaming ones by HBM.
+#include "qai_code.h"
 #include "qai_device.h"
 #include "qai_kernels.h"
 #include <algorithm>
@@ -621,45 +622,17 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
         // copy there waits for the loads: the prefetch would be lost.
         auto load = [&](int64_t zz, int64_t yy, uint32_t (&r)[V]) -> bool {
             const bool ok = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
-            if (CODED) {
-                // the lane's V indices of the line: segment s of the row (the
-                // G = 32 / V lanes of a segment are consecutive), the prediction
-                // from the prior value undone by a prefix sum over the segment
-                constexpr int G = 32 / V;
-                const __amdgpu_buffer_rsrc_t pay = __builtin_amdgcn_make_buffer_rsrc(
-                    const_cast<uint32_t*>(a.cpay), (short)0, (int)a.cpay_bytes, 0x00020000);
+            if constexpr (CODED) {
+                // the lane's V indices of the line: its share of segment x0 / 32
+                // of the row (the 32 / V lanes of a segment are consecutive)
                 const int64_t row = (ok ? zz : 0) * ny + (ok ? yy : 0);
                 const int sg = min(x0 >> 5, (int)a.segs_row - 1);
-                const int64_t ks = row * a.segs_row + sg;
-                const uint64_t mt = a.cmeta[ks];
-                const int bw = (int)(mt & 0xFFu);
-                const uint32_t wo = (uint32_t)(mt >> 8);
-                const uint64_t mask = (bw >= 32) ? 0xFFFFFFFFull : ((1ull << bw) - 1ull);
-                const int p0 = x0 - (sg << 5);
-                int32_t acc = 0;
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    const int i = p0 + j;
-                    const uint32_t bit = (uint32_t)(i > 0 ? i - 1 : 0) * (uint32_t)bw;
-                    const uint32_t wd = bw ? (wo + (bit >> 5)) * 4u : 0x80000000u; // width 0: no payload read
-                    const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b32(pay, wd, 0, 0);
-                    const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b32(pay, wd + 4u, 0, 0);
-                    const uint32_t zc = (i > 0) ? (uint32_t)(((((uint64_t)hi << 32) | lo) >> (bit & 31u)) & mask) : 0u;
-                    acc += (int32_t)((zc >> 1) ^ (0u - (zc & 1u)));
-                    r[j] = (uint32_t)acc;
-                }
-                // exclusive scan of the lanes' totals within the segment's lane group
-                int32_t inc = acc;
-#pragma unroll
-                for (int d = 1; d < G; d <<= 1) {
-                    const int32_t t = __shfl_up(inc, d, G);
-                    if ((lane & (G - 1)) >= d)
-                        inc += t;
-                }
-                const int32_t basev = a.cbase[ks] + (inc - acc);
+                int32_t qv[V];
+                decode_share<V>(a.cbase, a.cmeta, payload_rsrc(a.cpay, a.cpay_bytes), row * a.segs_row + sg,
+                                x0 - (sg << 5), lane, qv);
 #pragma unroll
                 for (int j = 0; j < V; ++j)
-                    r[j] = (uint32_t)(basev + (int32_t)r[j]);
+                    r[j] = (uint32_t)qv[j];
                 return ok;
             }
             const uint32_t* p = src + ((ok ? zz : 0) * ny + (ok ? yy : 0)) * (int64_t)nx;

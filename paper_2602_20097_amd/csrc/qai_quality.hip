@@ -12,8 +12,8 @@
 // and the squared differences (PSNR, MSE); the second marches z-planes
 // through tiles of 16 x 16 window positions: a plane's row sums over the
 // x-window (FP64, from the plane tile staged in LDS), then the y-window sums
-// per position, then running sums over the last 7 planes in registers; each
-// window that completes on a plane adds its SSIM.  All sums are FP64 and the
+// per position, added to the (at most four) windows along z the plane belongs
+// to; each window that completes on a plane adds its SSIM.  All sums are FP64 and the
 // reduction order is fixed by the shape, so results are deterministic.
 #include <math.h>
 
@@ -155,12 +155,18 @@ __global__ __launch_bounds__(kRedThreads) void k_range_final(const double* __res
 
 // Second pass.  Block (tx, ty, cz): window positions wy in [ty*16, +16),
 // wx in [tx*16, +16), wz in [cz*32, +32); thread (ly, lx) owns one (wy, wx).
+// Planes are taken in groups of eight aligned to z = 0 mod 8: a plane
+// belongs to the windows starting at most 6 planes before it, at most four
+// of them, each held in accumulator slot (start / 2) mod 4 -- a static index
+// within the group.  The next plane's tile is loaded into registers while the
+// current one is summed (two LDS tile buffers, two barriers per plane).
 constexpr int kRows = (kTile - 1) * kQS + kQW; // 37 staged rows / columns per plane
+constexpr int kStage = (kRows * kRows + 255) / 256; // tile elements per thread and field
 
 __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a, const float* __restrict__ b, QGeom g,
                                               const double* __restrict__ rng, double* __restrict__ part)
 {
-    __shared__ float ta[kRows * kRows], tb[kRows * kRows];
+    __shared__ float ta[2][kRows * kRows], tb[2][kRows * kRows];
     __shared__ double xs[5][kRows][kTile];
     __shared__ double sh[256];
     const int t = threadIdx.x;
@@ -171,43 +177,66 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a, const
     const int64_t x0 = bx * kTile * kQS, y0 = by * kTile * kQS;
     const int cols = (int)min((int64_t)kRows, g.nx - x0), rows = (int)min((int64_t)kRows, g.ny - y0);
     const int64_t wz0 = cz * kZChunk, wz1 = min(g.pz, wz0 + kZChunk);
-    const int64_t z0 = wz0 * kQS, z1 = (wz1 - 1) * kQS + g.wz; // planes this block reads
+    const int64_t z0 = wz0 * kQS, z1 = (wz1 - 1) * kQS + g.wz; // planes this block reads; z0 = 0 mod 8
     const double lo = rng[0];
     const double inv = 1.0 / (rng[1] - rng[0]);
     const int m = g.wz * g.wy * g.wx;
     const double rm = 1.0 / (double)m, rm1 = 1.0 / (double)(m - 1);
-    // x-window sums this thread computes: items t, t + 256, t + 512 of rows x kTile
-    double ring[kQW][5];
+    const int wz = g.wz;
+    double acc[4][5];
 #pragma unroll
-    for (int k = 0; k < kQW; ++k)
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int q = 0; q < 5; ++q)
-            ring[k][q] = 0.0;
-    double run[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    double acc = 0.0;
+            acc[k][q] = 0.0;
+    double total = 0.0;
 
-    for (int64_t zb = z0; zb < z1; zb += kQW) {
+    // this thread's share of a plane tile: elements t, t + 256, ... of rows x cols
+    float ra[kStage], rb[kStage];
+    auto fetch = [&](int64_t z) {
+        const int64_t pb = (min(z, g.nz - 1) * g.ny + y0) * g.nx + x0;
 #pragma unroll
-        for (int k = 0; k < kQW; ++k) {
+        for (int e = 0; e < kStage; ++e) {
+            const int i = t + e * 256;
+            const int r = i / cols, c = i - r * cols;
+            const bool in = i < rows * cols;
+            const int64_t gi = pb + (in ? (int64_t)r * g.nx + c : 0);
+            ra[e] = a[gi];
+            rb[e] = b[gi];
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < kStage; ++e) {
+            const int i = t + e * 256;
+            if (i < rows * cols) {
+                const int r = i / cols, c = i - r * cols;
+                ta[buf][r * kRows + c] = ra[e];
+                tb[buf][r * kRows + c] = rb[e];
+            }
+        }
+    };
+
+    fetch(z0);
+    int buf = 0;
+    for (int64_t zb = z0; zb < z1; zb += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
             const int64_t z = zb + k;
             if (z >= z1)
                 break;
-            // stage the plane tile of both fields
-            const int64_t pb = (z * g.ny + y0) * g.nx + x0;
-            for (int i = t; i < rows * cols; i += 256) {
-                const int r = i / cols, c = i - r * cols;
-                ta[r * kRows + c] = a[pb + (int64_t)r * g.nx + c];
-                tb[r * kRows + c] = b[pb + (int64_t)r * g.nx + c];
-            }
+            stage(buf);
             __syncthreads();
+            if (z + 1 < z1)
+                fetch(z + 1);
             // row sums over the x-window at every window column of the tile
             for (int i = t; i < rows * kTile; i += 256) {
-                const int r = i >> 4, c = (i & (kTile - 1)) * kQS;
+                const int r = i >> 4, cc = i & (kTile - 1), c = cc * kQS;
                 double su = 0.0, sv = 0.0, suu = 0.0, svv = 0.0, suv = 0.0;
                 if (c + g.wx <= cols) {
                     for (int j = 0; j < g.wx; ++j) {
-                        const double u = ((double)ta[r * kRows + c + j] - lo) * inv;
-                        const double v = ((double)tb[r * kRows + c + j] - lo) * inv;
+                        const double u = ((double)ta[buf][r * kRows + c + j] - lo) * inv;
+                        const double v = ((double)tb[buf][r * kRows + c + j] - lo) * inv;
                         su += u;
                         sv += v;
                         suu += u * u;
@@ -215,12 +244,11 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a, const
                         suv += u * v;
                     }
                 }
-                const int rr = r, cc = i & (kTile - 1);
-                xs[0][rr][cc] = su;
-                xs[1][rr][cc] = sv;
-                xs[2][rr][cc] = suu;
-                xs[3][rr][cc] = svv;
-                xs[4][rr][cc] = suv;
+                xs[0][r][cc] = su;
+                xs[1][r][cc] = sv;
+                xs[2][r][cc] = suu;
+                xs[3][r][cc] = svv;
+                xs[4][r][cc] = suv;
             }
             __syncthreads();
             double pl[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -230,25 +258,33 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a, const
                     for (int q = 0; q < 5; ++q)
                         pl[q] += xs[q][ly * kQS + j][lx];
             }
-            // running sums over the last wz planes (a plane leaves after 7)
+            // the windows starting d = 0..6 planes before z (even starts only)
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                run[q] += pl[q] - ring[k][q];
-                ring[k][q] = pl[q];
+            for (int d = 0; d < kQW; ++d) {
+                if (((k - d) & 1) != 0)
+                    continue;                           // odd start: not a window
+                const int slot = ((k - d + 8) >> 1) & 3; // static: zb = 0 mod 8
+                const int64_t st = z - d;
+                if (d >= wz || st < z0 || st < 0 || st / kQS >= wz1)
+                    continue;                           // uniform over the block
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+                    acc[slot][q] = (d == 0 ? 0.0 : acc[slot][q]) + pl[q];
+                if (d == wz - 1 && mine) {
+                    const double* w = acc[slot];
+                    const double mu = w[0] * rm, mv = w[1] * rm;
+                    const double vu = (w[2] - w[0] * mu) * rm1, vv = (w[3] - w[1] * mv) * rm1;
+                    const double cv = (w[4] - w[0] * mv) * rm1;
+                    total += ((2.0 * mu * mv + 1e-4) * (2.0 * cv + 9e-4)) /
+                             ((mu * mu + mv * mv + 1e-4) * (vu + vv + 9e-4));
+                }
             }
-            const int64_t ws = z - g.wz + 1; // window start completed by this plane
-            if (mine && ws >= wz0 * kQS && ws >= 0 && (ws % kQS) == 0 && ws / kQS < wz1) {
-                const double mu = run[0] * rm, mv = run[1] * rm;
-                const double vu = (run[2] - run[0] * mu) * rm1, vv = (run[3] - run[1] * mv) * rm1;
-                const double cv = (run[4] - run[0] * mv) * rm1;
-                acc += ((2.0 * mu * mv + 1e-4) * (2.0 * cv + 9e-4)) / ((mu * mu + mv * mv + 1e-4) * (vu + vv + 9e-4));
-            }
-            __syncthreads();
+            buf ^= 1;
         }
     }
-    acc = block_sum(acc, sh);
+    total = block_sum(total, sh);
     if (t == 0)
-        part[(cz * g.tiles_y + by) * g.tiles_x + bx] = acc;
+        part[(cz * g.tiles_y + by) * g.tiles_x + bx] = total;
 }
 
 __global__ __launch_bounds__(256) void k_ssim_final(const double* __restrict__ part, int64_t nb, double windows,

@@ -153,6 +153,48 @@ hipError_t tune_field(Plan1& p, const Tuning& base, hipStream_t s, Tuning& best,
     return e;
 }
 
+// Variants of a shape's setting for one field: the pass algorithms of both
+// EDTs, whose best choice follows the field's boundary density (sparse
+// boundaries: longer distances) more than its shape.
+hipError_t refine_field(Plan1& p, const Tuning& shape_best, hipStream_t s, Tuning& best)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess)
+        e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        if (a)
+            (void)hipEventDestroy(a);
+        return e;
+    }
+    std::vector<Tuning> cands;
+    cands.push_back(shape_best);
+    const int e1s[2] = {-1, 1}, e2s[3] = {-1, 3, 1};
+    for (int x : e1s)
+        for (int y : e2s) {
+            Tuning t = shape_best;
+            for (int k = 1; k < 3; ++k) {
+                t.edt1_algo[k] = x;
+                t.env_algo[k] = y;
+            }
+            cands.push_back(t);
+        }
+    float best_ms = 1e30f;
+    best = shape_best;
+    for (const Tuning& t : cands) {
+        float ms = 0.0f;
+        if ((e = time_run(p, t, s, a, b, ms)) != hipSuccess)
+            break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return e;
+}
+
 } // namespace qai
 
 namespace {

@@ -110,7 +110,7 @@ def test_batch_workspace_and_argument_errors(lib):
     h = ctypes.c_void_p()
     big = 1 << 30
     assert lib.qai_batch_plan_create(0, fp, d1, eb, op, None, 0, FAKE, big, None, ctypes.byref(h)) == -1
-    assert lib.qai_batch_plan_create(1, fp, d1, eb, op, None, 2, FAKE, big, None, ctypes.byref(h)) == -1
+    assert lib.qai_batch_plan_create(1, fp, d1, eb, op, None, 4, FAKE, big, None, ctypes.byref(h)) == -1
     assert lib.qai_batch_plan_create(1, fp, bad, eb, op, None, 0, FAKE, big, None, ctypes.byref(h)) == -2
     ebz = (ctypes.c_float * 1)(0.0)
     assert lib.qai_batch_plan_create(1, fp, d1, ebz, op, None, 0, FAKE, big, None, ctypes.byref(h)) == -1
