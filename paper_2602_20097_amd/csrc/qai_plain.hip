@@ -585,6 +585,9 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
     const bool hy = ny > 1, hz = nz > 1, hx = nx > 1;
     const uint32_t* __restrict__ src = (SA) ? (const uint32_t*)a.xq : a.w1;
     const int x0 = V * lane;               // first voxel of the lane
+    const int cs = CODED ? min(x0 >> 5, (int)a.segs_row - 1) : 0;
+    const int cp0 = x0 - (cs << 5);
+    const __amdgpu_buffer_rsrc_t prs = payload_rsrc(CODED ? a.cpay : nullptr, CODED ? a.cpay_bytes : 0u);
     // stencil range along x: the interior when the axis exists
     const int xmax = hx ? nx - 2 : nx - 1;
     const bool first_in = x0 >= (hx ? 1 : 0);
@@ -614,6 +617,31 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
         const bool halo = hy && (wave == 0 || wave == WPB - 1);
         const int hrow = (wave == 0) ? 0 : R - 1;
 
+        // Coded input: a line's decode in flight -- its segment head, the
+        // payload words of the lane's share, whether the line lies in the field.
+        // The lane's share of its row: segment cs = x0 / 32 (lanes past the
+        // row's end take the last segment; their values are not used), voxels
+        // [cp0, cp0 + V) of it; the 32 / V lanes of a segment are consecutive.
+        struct Pend {
+            CodeHead h;
+            uint32_t w4[4];
+            bool ok;
+        };
+        auto seg_of = [&](int64_t zz, int64_t yy, bool ok) -> int64_t {
+            return ((ok ? zz : 0) * ny + (ok ? yy : 0)) * a.segs_row + cs;
+        };
+        // step one: the meta word only (the first index comes with step two)
+        auto start = [&](int64_t zz, int64_t yy) -> Pend {
+            Pend pd;
+            pd.ok = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
+            pd.h.mt = a.cmeta[seg_of(zz, yy, pd.ok)];
+            return pd;
+        };
+        // step two: the first index and the payload words
+        auto fetch = [&](Pend& pd, int64_t zz, int64_t yy) {
+            pd.h.b0 = a.cbase[seg_of(zz, yy, pd.ok)];
+            code_words<V>(prs, pd.h, cp0, pd.w4);
+        };
         // Loads go to valid addresses without branching: a line outside the
         // field reads line 0 and a group of words past the end of the line the
         // line's first group; keys() substitutes 0 for them (nx is a multiple
@@ -623,17 +651,16 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
         auto load = [&](int64_t zz, int64_t yy, uint32_t (&r)[V]) -> bool {
             const bool ok = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
             if constexpr (CODED) {
-                // the lane's V indices of the line: its share of segment x0 / 32
-                // of the row (the 32 / V lanes of a segment are consecutive)
-                const int64_t row = (ok ? zz : 0) * ny + (ok ? yy : 0);
-                const int sg = min(x0 >> 5, (int)a.segs_row - 1);
+                // the lane's V indices of the line, decoded at once (the
+                // prologue); the plane loop pipelines the steps (Pend)
+                Pend pd = start(zz, yy);
+                fetch(pd, zz, yy);
                 int32_t qv[V];
-                decode_share<V>(a.cbase, a.cmeta, payload_rsrc(a.cpay, a.cpay_bytes), row * a.segs_row + sg,
-                                x0 - (sg << 5), lane, qv);
+                code_finish<V>(prs, pd.h, pd.w4, cp0, lane, qv);
 #pragma unroll
                 for (int j = 0; j < V; ++j)
                     r[j] = (uint32_t)qv[j];
-                return ok;
+                return pd.ok;
             }
             const uint32_t* p = src + ((ok ? zz : 0) * ny + (ok ? yy : 0)) * (int64_t)nx;
 #pragma unroll
@@ -700,9 +727,24 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
             keys(hraw, hok, H);
             put(0, hrow, H);
         }
-        rok = load(z0 + 2, y, raw);
-        if (halo)
-            hok = load(z0 + 1, yh, hraw);
+        // coded input, decodes in flight: own line z0 + 2 and halo line z0 + 1
+        // with their payload words requested, own line z0 + 3 and halo line
+        // z0 + 2 with their heads requested (the plane loop keeps this shape)
+        Pend po{}, ph{}, pon{}, phn{};
+        if constexpr (CODED) {
+            po = start(z0 + 2, y);
+            fetch(po, z0 + 2, y);
+            pon = start(z0 + 3, y);
+            if (halo) {
+                ph = start(z0 + 1, yh);
+                fetch(ph, z0 + 1, yh);
+                phn = start(z0 + 2, yh);
+            }
+        } else {
+            rok = load(z0 + 2, y, raw);
+            if (halo)
+                hok = load(z0 + 1, yh, hraw);
+        }
         lds_barrier();
 
         int cur = 0;
@@ -842,6 +884,21 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                     P0[j] = P1[j];
                     P1[j] = P2[j];
                 }
+                if constexpr (CODED) {
+                    int32_t qv[V];
+                    code_finish<V>(prs, po.h, po.w4, cp0, lane, qv);
+#pragma unroll
+                    for (int j = 0; j < V; ++j)
+                        raw[j] = (uint32_t)qv[j];
+                    rok = po.ok;
+                    if (halo) {
+                        code_finish<V>(prs, ph.h, ph.w4, cp0, lane, qv);
+#pragma unroll
+                        for (int j = 0; j < V; ++j)
+                            hraw[j] = (uint32_t)qv[j];
+                        hok = ph.ok;
+                    }
+                }
                 keys(raw, rok, P2);
                 put(cur ^ 1, wave + 1, P1);
                 if (halo) {
@@ -849,9 +906,20 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                     keys(hraw, hok, H);
                     put(cur ^ 1, hrow, H);
                 }
-                rok = load(z + 3, y, raw);
-                if (halo)
-                    hok = load(z + 2, yh, hraw);
+                if constexpr (CODED) {
+                    po = pon;
+                    fetch(po, z + 3, y);
+                    pon = start(z + 4, y);
+                    if (halo) {
+                        ph = phn;
+                        fetch(ph, z + 2, yh);
+                        phn = start(z + 3, yh);
+                    }
+                } else {
+                    rok = load(z + 3, y, raw);
+                    if (halo)
+                        hok = load(z + 2, yh, hraw);
+                }
             }
             lds_barrier();
             cur ^= 1;

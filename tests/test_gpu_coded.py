@@ -58,3 +58,30 @@ def test_out_of_range_indices_raise_the_status_flag():
     ws2 = qai.new_workspace(q.shape)
     qai.mitigate_coded(qai.upload_code(synth.encode_indices(q)), 0.5, workspace=ws2)
     assert qai.device_status(ws2) == 0
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 512), (4, 6, 256), (3, 5, 128), (3, 5, 64), (2, 3, 600), (1, 2, 700)])
+def test_wide_and_mixed_segment_widths(shape):
+    """Rough rows (differences up to 2^21: widths past 12 bits, where a lane of
+    eight voxels reads two words per difference) beside smooth ones, so that the
+    lanes of one wave take both decode paths."""
+    print(f"coded wide case {shape}", flush=True)
+    rng = np.random.default_rng(83)
+    x32, xq, q, eb = synth.quantize(synth.grf(shape, 3.0, 84), 1e-3)
+    q = q.copy()
+    rough = rng.random(shape[:2]) < 0.5
+    rough.flat[0], rough.flat[-1] = True, False
+    noise = rng.integers(-(1 << 20), (1 << 20) + 1, size=shape, dtype=np.int64)
+    q[rough] = np.clip(q[rough] + noise[rough], -(1 << 21), 1 << 21).astype(np.int32)
+    xq = (2.0 * eb * q.astype(np.float64)).astype(np.float32)
+    code = synth.encode_indices(q)
+    meta = code["meta"].astype(np.int64)
+    assert (meta & 0xFF).max() > 12 and (meta & 0xFF).min() <= 12
+    dc = qai.upload_code(code)
+    t = torch.from_numpy(xq).cuda()
+    dec = qai.decode(dc, eb)
+    ref = qai.mitigate(t, eb)
+    out = qai.mitigate_coded(dc, eb)
+    torch.cuda.synchronize()
+    assert torch.equal(dec.view(torch.int32), t.view(torch.int32))
+    assert torch.equal(out.view(torch.int32), ref.view(torch.int32))
