@@ -212,7 +212,9 @@ void qai_batch_plan_destroy(qai_batch_plan* plan);
 typedef struct qai_tuning {
     int32_t edt1_algo[2];  /* y and z passes of the first EDT: 0 streaming envelope, 1 windowed
                               search over LDS tiles, 2 banded envelope over LDS tiles,
-                              4 streaming outward search (short distances); -1 (the default)
+                              4 streaming outward search (short distances), 5 outward search
+                              per voxel from the pass input (short distances, any number
+                              of column tiles); -1 (the default)
                               picks per pass: 1 when the pass has fewer than 4096 tiles of
                               64 columns, else 4; on a 3-D field with both passes at -1 they
                               run as one search over (y, z) offsets, with the separable passes
@@ -228,9 +230,11 @@ typedef struct qai_tuning {
     int32_t edt2_ring;
     int32_t tile_log2[2];  /* log2 of x-columns per tile of the tiled variants, y and z (-1: auto) */
     int32_t seed_rows;     /* x-lines (wavefronts) per workgroup of the LDS-slab seed passes
-                              (1..8); 0 selects the register-resident variant (8 lines per
-                              workgroup) wherever x-lines hold at most 512 voxels; -1 the
-                              line-per-wave variant (neighbour lines read through the caches) */
+                              (1..8); 0 selects the register-resident variant (a wave per
+                              line of up to 512 voxels, two, four or eight waves per line of
+                              up to 1024, 2048 or 4096) wherever x-lines hold at most 4096
+                              voxels; -1 the line-per-wave variant (neighbour lines read
+                              through the caches) */
     int32_t seed_planes;   /* z-planes marched per workgroup of the seed passes (>= 1) */
     int32_t window_threads; /* threads per workgroup of the windowed variant (64..1024) */
     int32_t force_wide;    /* 0 (the default): each kernel picks 32-bit buffer offsets and 32-bit
@@ -326,7 +330,8 @@ int qai_decode(const qai_coded* code, const int64_t dims[3], float eb, float* xq
 
 /* qai_mitigate_ex from coded indices (no taps): out receives the result; the
  * first seed pass decodes the indices it reads (lines of up to 512 voxels with
- * ceil(nx / 64) in {1, 2, 4, 8}; other shapes decode into out first) and writes
+ * ceil(nx / 64) in {1, 2, 4, 8}, and lines of 513 to 2048 voxels; other shapes
+ * decode into out first) and writes
  * x' into out, which the later stages read in place.  ws as for
  * qai_mitigate_ex; results equal qai_mitigate_ex on the decoded field. */
 int qai_mitigate_coded(const qai_coded* code, const int64_t dims[3], float eb, const qai_params* params, void* ws,

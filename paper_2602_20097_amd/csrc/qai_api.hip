@@ -201,9 +201,9 @@ int abi_to_tuning(const qai_tuning* in, Tuning& t)
 {
     default_tuning(t);
     for (int k = 0; k < 2; ++k) {
-        if (in->edt1_algo[k] < -1 || in->edt1_algo[k] > 4 || in->edt1_algo[k] == 3 || in->edt2_algo[k] < -1 ||
-            in->edt2_algo[k] > 4)
-            return fail(QAI_EINVAL, "algorithm choice: -1 (auto), 0, 1, 2 or 4 for the first EDT, -1..4 for the second");
+        if (in->edt1_algo[k] < -1 || in->edt1_algo[k] > 5 || in->edt1_algo[k] == 3 || in->edt2_algo[k] < -1 ||
+            in->edt2_algo[k] > 5)
+            return fail(QAI_EINVAL, "algorithm choice: -1 (auto), 0, 1, 2, 4 or 5 for the first EDT, -1..5 for the second");
         if (in->tile_log2[k] < -1 || in->tile_log2[k] > 6)
             return fail(QAI_EINVAL, "tile_log2 must be in [-1, 6]");
     }

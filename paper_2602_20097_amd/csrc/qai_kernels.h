@@ -112,6 +112,10 @@ void default_tuning(Tuning& t);
 // shape (axis 1 = y, 2 = z); an explicit choice is returned unchanged.
 int resolve_algo(int want, bool first_edt, int axis, int64_t nz, int64_t ny, int64_t nx);
 
+// Longest x-line of the register-resident seed pass (k_seed_lane): lines of
+// up to 512 voxels take one wave, longer ones two, four or eight.
+constexpr int64_t kSeedLaneMaxX = 4096;
+
 struct Plan1;
 
 // Per-shape tuning cache (filled by the autotuner, saved to and loaded from a

@@ -565,26 +565,36 @@ __device__ __forceinline__ int32_t raw_word_d1(const uint32_t* w1, int64_t i)
 // read and written VW words per access (VW divides V and nx).  LDS lines are
 // lane-major: voxel V l + j at j * 64 + l, so every LDS access of a wave is
 // 64 consecutive words.
-template <int MODE, int V, int WPB, int VW, bool TAPS>
+// Lines of more than 512 voxels (P > 1): P waves share a line, wave p owning
+// its piece [512 p, 512 p + 512) (V = 8); the +-x neighbours across a piece's
+// ends come from the LDS line, and the x pass's carries from the other pieces
+// from a per-plane exchange of each piece's first and last site (a second
+// barrier per plane).
+template <int MODE, int V, int WPB, int VW, bool TAPS, int P = 1>
 __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
 {
     static_assert(V % VW == 0, "vector width must divide the voxels per lane");
+    static_assert(P == 1 || (V == 8 && WPB % P == 0 && WPB / P >= 2), "pieces of 512 voxels, two lines or more per workgroup");
     // MODE 0: step A from the decompressed field; 2: step A from coded
     // indices (decoded here, x' = 2 eb q written to xout); 1: step C
     constexpr bool SA = MODE != 1, CODED = MODE == 2;
     static_assert(!CODED || (32 % V == 0 && !TAPS), "coded input: a lane's voxels lie in one 32-voxel segment");
-    constexpr int W = V * 64;
-    constexpr int R = WPB + 2;
+    constexpr int PW = V * 64;     // voxels of a wave's piece of its line
+    constexpr int W = PW * P;      // LDS words per line
+    constexpr int LP = WPB / P;    // lines per workgroup
+    constexpr int R = LP + 2;
     __shared__ uint32_t rows[2][R * W];
+    __shared__ uint32_t pinfo[P > 1 ? LP * P * 2 : 1]; // per piece: last site, first site
     __shared__ unsigned long long b1sum;
     const SeedArgs& a = A.s;
     const int nx = (int)a.nx;
     const int64_t ny = a.ny, nz = a.nz;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
+    const int line = wave / P, piece = wave % P;
     const bool hy = ny > 1, hz = nz > 1, hx = nx > 1;
     const uint32_t* __restrict__ src = (SA) ? (const uint32_t*)a.xq : a.w1;
-    const int x0 = V * lane;               // first voxel of the lane
+    const int x0 = piece * PW + V * lane;  // first voxel of the lane
     const int cs = CODED ? min(x0 >> 5, (int)a.segs_row - 1) : 0;
     const int cp0 = x0 - (cs << 5);
     const __amdgpu_buffer_rsrc_t prs = payload_rsrc(CODED ? a.cpay : nullptr, CODED ? a.cpay_bytes : 0u);
@@ -610,12 +620,12 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
     for (uint64_t t = blockIdx.x; t < nblocks; t += gridDim.x) {
         const uint64_t bl = xcd_remap(t, nblocks);
         const int64_t by = (int64_t)(bl % (uint64_t)A.nby), bz = (int64_t)(bl / (uint64_t)A.nby);
-        const int64_t y0 = by * WPB, z0 = bz * A.tz;
+        const int64_t y0 = by * LP, z0 = bz * A.tz;
         const int64_t z1 = min(nz, z0 + A.tz);
-        const int64_t y = y0 + wave;
-        const int64_t yh = (wave == 0) ? y0 - 1 : y0 + WPB;
-        const bool halo = hy && (wave == 0 || wave == WPB - 1);
-        const int hrow = (wave == 0) ? 0 : R - 1;
+        const int64_t y = y0 + line;
+        const int64_t yh = (line == 0) ? y0 - 1 : y0 + LP;
+        const bool halo = hy && (line == 0 || line == LP - 1);
+        const int hrow = (line == 0) ? 0 : R - 1;
 
         // Coded input: a line's decode in flight -- its segment head, the
         // payload words of the lane's share, whether the line lies in the field.
@@ -701,7 +711,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
         auto put = [&](int b, int row, const uint32_t (&k)[V]) {
 #pragma unroll
             for (int j = 0; j < V; ++j)
-                rows[b][row * W + j * 64 + lane] = k[j];
+                rows[b][row * W + piece * PW + j * 64 + lane] = k[j];
         };
 
         uint32_t raw[V], hraw[V];
@@ -721,25 +731,28 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                 P0[j] = P2[j] = P1[j];
         }
         lds_barrier();
-        put(0, wave + 1, P1);
+        put(0, line + 1, P1);
         if (halo) {
             uint32_t H[V];
             keys(hraw, hok, H);
             put(0, hrow, H);
         }
-        // coded input, decodes in flight: own line z0 + 2 and halo line z0 + 1
-        // with their payload words requested, own line z0 + 3 and halo line
-        // z0 + 2 with their heads requested (the plane loop keeps this shape)
-        Pend po{}, ph{}, pon{}, phn{};
+        // coded input, decodes in flight: own line z0 + 2 with its payload
+        // words requested (DEEP) or its head, own line z0 + 3 with its head
+        // requested (DEEP), halo line z0 + 1 with its head requested (the plane
+        // loop keeps this shape and requests the other payload words when it
+        // decodes their lines).  DEEP for whole lines: pieces of long lines
+        // leave no room for the extra registers
+        constexpr bool DEEP = false;
+        Pend po{}, ph{}, pon{};
         if constexpr (CODED) {
             po = start(z0 + 2, y);
-            fetch(po, z0 + 2, y);
-            pon = start(z0 + 3, y);
-            if (halo) {
-                ph = start(z0 + 1, yh);
-                fetch(ph, z0 + 1, yh);
-                phn = start(z0 + 2, yh);
+            if (DEEP) {
+                fetch(po, z0 + 2, y);
+                pon = start(z0 + 3, y);
             }
+            if (halo)
+                ph = start(z0 + 1, yh);
         } else {
             rok = load(z0 + 2, y, raw);
             if (halo)
@@ -749,117 +762,13 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
 
         int cur = 0;
         for (int64_t z = z0; z < z1; ++z) {
-            if (y < ny) {
-                const uint32_t* rc = &rows[cur][(wave + 1) * W];
-                const uint32_t* rym = hy ? rc - W : rc;
-                const uint32_t* ryp = hy ? rc + W : rc;
-                const bool line_in = (!hy || (y >= 1 && y <= ny - 2)) && (!hz || (z >= 1 && z <= nz - 2));
-                // the neighbours across the lane's two ends (a flat x axis: itself)
-                const uint32_t kleft = hx ? rc[(V - 1) * 64 + (lane > 0 ? lane - 1 : 0)] : P1[0];
-                const uint32_t kright = hx ? rc[lane < 63 ? lane + 1 : 63] : P1[V - 1];
-                bool st[V];      // voxel x0 + j is a site
-                uint32_t sv[V];  // its site value
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    const int x = x0 + j;
-                    const uint32_t kc = P1[j];
-                    const uint32_t kxp = j + 1 < V ? P1[j + 1] : kright;
-                    const uint32_t kxm = j > 0 ? P1[j - 1] : kleft;
-                    const uint32_t kyp = ryp[j * 64 + lane], kym = rym[j * 64 + lane];
-                    const uint32_t kzp = P2[j], kzm = P0[j];
-                    const bool in = line_in && x <= xmax && (j > 0 || first_in);
-                    uint32_t code = 0u;
-                    if (SA) {
-                        // Algorithm 2 (see k_seed_slab): g is the first neighbour that
-                        // differs from the voxel, in the order +x, -x, +y, -y, +z, -z
-                        uint32_t g = (kxp != kc) ? kxp : kxm;
-                        g = (g != kc) ? g : ((kyp != kc) ? kyp : kym);
-                        g = (g != kc) ? g : ((kzp != kc) ? kzp : kzm);
-                        // some axis differs by 2 or more: kp - km is not in {-1, 0, 1},
-                        // i.e. kp - km + 1 (mod 2^32) exceeds 2
-                        const bool steep = (kxp - kxm + 1u > 2u) | (kyp - kym + 1u > 2u) | (kzp - kzm + 1u > 2u);
-                        st[j] = in && g != kc;
-                        code = steep ? 0u : (g > kc ? 1u : 2u);
-                        if (TAPS && x < nx) {
-                            const int64_t i = (z * ny + y) * (int64_t)nx + x;
-                            const int sgn = st[j] ? (code == 1u ? 1 : (code == 2u ? -1 : 0)) : 0;
-                            if (a.tq) a.tq[i] = (int32_t)(kc ^ 0x80000000u);
-                            if (a.tb1) a.tb1[i] = st[j] ? 1 : 0;
-                            if (a.tsb) a.tsb[i] = (int8_t)sgn;
-                        }
-                    } else {
-                        // Algorithm 3's GetBoundary(S) (see k_seed_slab)
-                        const uint32_t diff = (kxp ^ kc) | (kxm ^ kc) | (kyp ^ kc) | (kym ^ kc) | (kzp ^ kc) | (kzm ^ kc);
-                        st[j] = in && !(kc & 4u) && (diff & 3u) != 0u;
-                        if (TAPS && x < nx) {
-                            const int64_t i = (z * ny + y) * (int64_t)nx + x;
-                            if (a.ts) a.ts[i] = (int8_t)((kc & 3u) == 1u ? 1 : ((kc & 3u) == 2u ? -1 : 0));
-                            if (a.td1) a.td1[i] = raw_word_d1(a.w1, i);
-                            if (a.tb2) a.tb2[i] = st[j] ? 1 : 0;
-                        }
-                    }
-                    sv[j] = ((uint32_t)(x + 4096) << 2) | code;
-                    if (SA && j == 0)
-                        nb1 += (uint32_t)__popcll(__ballot(st[0]));
-                }
-                // nearest site at or before / at or after each voxel among the
-                // lane's own, then the carries: the last site of the nearest lane
-                // below holding one, the first of the nearest lane above (a value
-                // from below is smaller than any own one, from above larger)
-                uint32_t lv[V], rv[V];
-                uint32_t L = 0u, Rr = NONE_R;
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    L = st[j] ? sv[j] : L;
-                    lv[j] = L;
-                }
-#pragma unroll
-                for (int j = V - 1; j >= 0; --j) {
-                    Rr = st[j] ? sv[j] : Rr;
-                    rv[j] = Rr;
-                }
-                const uint64_t m = __ballot(lv[V - 1] != 0u);
-                const uint64_t ml = m & lower, mr = m & upper;
-                const int sl = ml ? 63 - __clzll(ml) : 0;
-                const int sr = mr ? __ffsll((unsigned long long)mr) - 1 : 0;
-                const uint32_t cl = (uint32_t)__shfl((int)lv[V - 1], sl);
-                const uint32_t cr = (uint32_t)__shfl((int)rv[0], sr);
-                const uint32_t carry_l = ml ? cl : 0u, carry_r = mr ? cr : NONE_R;
-                uint32_t word[V];
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    // sweep result: nearest of the two, ties to the left site;
-                    // distances in units of 4 (d4 = 4 d, d4^2 / 4 = d^2 << 2)
-                    const uint32_t Lj = max(lv[j], carry_l), Rj = min(rv[j], carry_r);
-                    const uint32_t xb4 = (uint32_t)(x0 + j + 4096) << 2;
-                    const uint32_t cm = (SA) ? ~3u : ~0u; // mode 1 values carry no code
-                    const uint32_t dl4 = xb4 - (Lj & cm), dr4 = (Rj & cm) - xb4;
-                    const bool left = dl4 <= dr4;
-                    const uint32_t d4 = left ? dl4 : dr4;
-                    const uint32_t cd = (SA) ? ((left ? Lj : Rj) & 3u) : 0u;
-                    word[j] = (__umul24(d4, d4) >> 2) | cd;
-                }
-                if (m == 0ull) {
-                    // no site on the line
-#pragma unroll
-                    for (int j = 0; j < V; ++j)
-                        word[j] = QAI_WORD_INF;
-                }
-                uint32_t* const wrow = a.wout + (z * ny + y) * (int64_t)nx + x0;
-#pragma unroll
-                for (int j = 0; j < V; j += VW) {
-                    if (x0 + j < nx) {
-                        if (VW == 4)
-                            *(uint4*)(wrow + j) = make_uint4(word[j], word[j + 1], word[j + 2], word[j + 3]);
-                        else if (VW == 2)
-                            *(uint2*)(wrow + j) = make_uint2(word[j], word[j + 1]);
-                        else
-                            wrow[j] = word[j];
-                    }
-                }
-                if (CODED) {
+            // (pieces of longer lines: every wave takes part, for the barrier
+            // of the site exchange; a line past the field's end stores nothing)
+            if (P > 1 || y < ny) {
+                const bool act = y < ny;
+                if (CODED && act) {
                     // the decompressed value of the wave's own line, x' = 2 eb q
-                    // (exact product, one rounding: the decompressor's value)
+                    // (the exact product rounded once: the decompressor's value)
                     float* const xrow = a.xout + (z * ny + y) * (int64_t)nx + x0;
 #pragma unroll
                     for (int j = 0; j < V; j += VW) {
@@ -877,6 +786,145 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                         }
                     }
                 }
+                const uint32_t* rc = &rows[cur][(line + 1) * W + piece * PW];
+                const uint32_t* rym = hy ? rc - W : rc;
+                const uint32_t* ryp = hy ? rc + W : rc;
+                const bool line_in = (!hy || (y >= 1 && y <= ny - 2)) && (!hz || (z >= 1 && z <= nz - 2));
+                // the neighbours across the lane's two ends (a flat x axis: itself)
+                // (a piece of a longer line: across its ends, the neighbouring
+                // pieces' end voxels)
+                uint32_t kleft = P1[0], kright = P1[V - 1];
+                if (hx) {
+                    if constexpr (P == 1) {
+                        kleft = rc[(V - 1) * 64 + (lane > 0 ? lane - 1 : 0)];
+                        kright = rc[lane < 63 ? lane + 1 : 63];
+                    } else {
+                        kleft = rc[lane > 0 ? (V - 1) * 64 + lane - 1 : (piece > 0 ? -1 : (V - 1) * 64)];
+                        kright = rc[lane < 63 ? lane + 1 : (piece < P - 1 ? PW : 63)];
+                    }
+                }
+                bool st[V];      // voxel x0 + j is a site
+                uint32_t sv[V];  // its site value
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const int x = x0 + j;
+                    const uint32_t kc = P1[j];
+                    const uint32_t kxp = j + 1 < V ? P1[j + 1] : kright;
+                    const uint32_t kxm = j > 0 ? P1[j - 1] : kleft;
+                    const uint32_t kyp = ryp[j * 64 + lane], kym = rym[j * 64 + lane];
+                    const uint32_t kzp = P2[j], kzm = P0[j];
+                    const bool in = act && line_in && x <= xmax && (j > 0 || first_in);
+                    uint32_t code = 0u;
+                    if (SA) {
+                        // Algorithm 2 (see k_seed_slab): g is the first neighbour that
+                        // differs from the voxel, in the order +x, -x, +y, -y, +z, -z
+                        uint32_t g = (kxp != kc) ? kxp : kxm;
+                        g = (g != kc) ? g : ((kyp != kc) ? kyp : kym);
+                        g = (g != kc) ? g : ((kzp != kc) ? kzp : kzm);
+                        // some axis differs by 2 or more: kp - km is not in {-1, 0, 1},
+                        // i.e. kp - km + 1 (mod 2^32) exceeds 2
+                        const bool steep = (kxp - kxm + 1u > 2u) | (kyp - kym + 1u > 2u) | (kzp - kzm + 1u > 2u);
+                        st[j] = in && g != kc;
+                        code = steep ? 0u : (g > kc ? 1u : 2u);
+                        if (TAPS && act && x < nx) {
+                            const int64_t i = (z * ny + y) * (int64_t)nx + x;
+                            const int sgn = st[j] ? (code == 1u ? 1 : (code == 2u ? -1 : 0)) : 0;
+                            if (a.tq) a.tq[i] = (int32_t)(kc ^ 0x80000000u);
+                            if (a.tb1) a.tb1[i] = st[j] ? 1 : 0;
+                            if (a.tsb) a.tsb[i] = (int8_t)sgn;
+                        }
+                    } else {
+                        // Algorithm 3's GetBoundary(S) (see k_seed_slab)
+                        const uint32_t diff = (kxp ^ kc) | (kxm ^ kc) | (kyp ^ kc) | (kym ^ kc) | (kzp ^ kc) | (kzm ^ kc);
+                        st[j] = in && !(kc & 4u) && (diff & 3u) != 0u;
+                        if (TAPS && act && x < nx) {
+                            const int64_t i = (z * ny + y) * (int64_t)nx + x;
+                            if (a.ts) a.ts[i] = (int8_t)((kc & 3u) == 1u ? 1 : ((kc & 3u) == 2u ? -1 : 0));
+                            if (a.td1) a.td1[i] = raw_word_d1(a.w1, i);
+                            if (a.tb2) a.tb2[i] = st[j] ? 1 : 0;
+                        }
+                    }
+                    sv[j] = ((uint32_t)(x + 4096) << 2) | code;
+                    if (SA && j == 0)
+                        nb1 += (uint32_t)__popcll(__ballot(st[0]));
+                }
+                // nearest site at or before / at or after each voxel among the
+                // lane's own
+                uint32_t lv[V], rv[V];
+                uint32_t L = 0u, Rr = NONE_R;
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    L = st[j] ? sv[j] : L;
+                    lv[j] = L;
+                }
+#pragma unroll
+                for (int j = V - 1; j >= 0; --j) {
+                    Rr = st[j] ? sv[j] : Rr;
+                    rv[j] = Rr;
+                }
+                const uint64_t m = __ballot(lv[V - 1] != 0u);
+                // nearest sites past the piece's ends (none for a whole line):
+                // each piece posts its last and first site, then reads the others'
+                uint32_t pl = 0u, pr = NONE_R;
+                if constexpr (P > 1) {
+                    const uint32_t last = (uint32_t)__shfl((int)lv[V - 1], m ? 63 - __clzll(m) : 0);
+                    const uint32_t first = (uint32_t)__shfl((int)rv[0], m ? __ffsll((unsigned long long)m) - 1 : 0);
+                    if (lane == 0) {
+                        pinfo[(line * P + piece) * 2] = m ? last : 0u;
+                        pinfo[(line * P + piece) * 2 + 1] = m ? first : NONE_R;
+                    }
+                    lds_barrier();
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        if (q < piece)
+                            pl = max(pl, pinfo[(line * P + q) * 2]);
+                        if (q > piece)
+                            pr = min(pr, pinfo[(line * P + q) * 2 + 1]);
+                    }
+                }
+                // the carries: the last site of the nearest lane below holding
+                // one, the first of the nearest lane above (a value from below is
+                // smaller than any own one, from above larger), else pl / pr
+                const uint64_t ml = m & lower, mr = m & upper;
+                const int sl = ml ? 63 - __clzll(ml) : 0;
+                const int sr = mr ? __ffsll((unsigned long long)mr) - 1 : 0;
+                const uint32_t cl = (uint32_t)__shfl((int)lv[V - 1], sl);
+                const uint32_t cr = (uint32_t)__shfl((int)rv[0], sr);
+                const uint32_t carry_l = ml ? cl : pl, carry_r = mr ? cr : pr;
+                uint32_t word[V];
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    // sweep result: nearest of the two, ties to the left site;
+                    // distances in units of 4 (d4 = 4 d, d4^2 / 4 = d^2 << 2)
+                    const uint32_t Lj = max(lv[j], carry_l), Rj = min(rv[j], carry_r);
+                    const uint32_t xb4 = (uint32_t)(x0 + j + 4096) << 2;
+                    const uint32_t cm = (SA) ? ~3u : ~0u; // mode 1 values carry no code
+                    const uint32_t dl4 = xb4 - (Lj & cm), dr4 = (Rj & cm) - xb4;
+                    const bool left = dl4 <= dr4;
+                    const uint32_t d4 = left ? dl4 : dr4;
+                    const uint32_t cd = (SA) ? ((left ? Lj : Rj) & 3u) : 0u;
+                    word[j] = (__umul24(d4, d4) >> 2) | cd;
+                }
+                if (m == 0ull && pl == 0u && pr == NONE_R) {
+                    // no site on the line
+#pragma unroll
+                    for (int j = 0; j < V; ++j)
+                        word[j] = QAI_WORD_INF;
+                }
+                if (act) {
+                    uint32_t* const wrow = a.wout + (z * ny + y) * (int64_t)nx + x0;
+#pragma unroll
+                    for (int j = 0; j < V; j += VW) {
+                        if (x0 + j < nx) {
+                            if (VW == 4)
+                                *(uint4*)(wrow + j) = make_uint4(word[j], word[j + 1], word[j + 2], word[j + 3]);
+                            else if (VW == 2)
+                                *(uint2*)(wrow + j) = make_uint2(word[j], word[j + 1]);
+                            else
+                                wrow[j] = word[j];
+                        }
+                    }
+                }
             }
             if (z + 1 < z1) {
 #pragma unroll
@@ -886,6 +934,10 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                 }
                 if constexpr (CODED) {
                     int32_t qv[V];
+                    if (!DEEP)
+                        fetch(po, z + 2, y);
+                    if (halo)
+                        fetch(ph, z + 1, yh);
                     code_finish<V>(prs, po.h, po.w4, cp0, lane, qv);
 #pragma unroll
                     for (int j = 0; j < V; ++j)
@@ -900,21 +952,22 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                     }
                 }
                 keys(raw, rok, P2);
-                put(cur ^ 1, wave + 1, P1);
+                put(cur ^ 1, line + 1, P1);
                 if (halo) {
                     uint32_t H[V];
                     keys(hraw, hok, H);
                     put(cur ^ 1, hrow, H);
                 }
                 if constexpr (CODED) {
-                    po = pon;
-                    fetch(po, z + 3, y);
-                    pon = start(z + 4, y);
-                    if (halo) {
-                        ph = phn;
-                        fetch(ph, z + 2, yh);
-                        phn = start(z + 3, yh);
+                    if (DEEP) {
+                        po = pon;
+                        fetch(po, z + 3, y);
+                        pon = start(z + 4, y);
+                    } else {
+                        po = start(z + 3, y);
                     }
+                    if (halo)
+                        ph = start(z + 2, yh);
                 } else {
                     rok = load(z + 3, y, raw);
                     if (halo)
@@ -991,7 +1044,21 @@ struct ZsArgs {
     int64_t nx, ny, nz;
     float eta_eb, power;
     bool blk;             // gy in the blocked layout [z][y/4][x][y%4] (else natural)
+    const unsigned long long* b1count; // when set, the layout is chosen on the device (blocked_layout)
 };
+
+// The y pass of the second EDT hands the needed-voxel search its words in the
+// blocked layout where B1 covers at least 90% of the field (the first seed
+// pass's estimate): needed voxels are then few, and the y pass's 16-byte
+// stores pay.  Elsewhere many voxels are needed (up to two thirds of a
+// field at rel. bound 1e-2) and the search's reads of natural rows touch a
+// quarter of the cache lines, so the natural layout goes.  The y pass and
+// the search read the same estimate and so agree on the layout.  The same
+// test stands the fused first-EDT search down (k_edt1_yz).
+__device__ __forceinline__ bool blocked_layout(const unsigned long long* b1count, uint64_t n)
+{
+    return *b1count * 10ull >= n * 9ull;
+}
 
 // index of voxel i's word in gy, and the distance between consecutive z-planes there
 template <bool BLK>
@@ -1126,7 +1193,7 @@ __device__ __forceinline__ bool interp_near(const ZsArgs& a, int64_t i, uint32_t
 }
 
 template <bool BUF, bool BLK>
-__global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
+__device__ __forceinline__ void interp_own(const ZsArgs& a)
 {
     const int64_t n = a.nx * a.ny * a.nz;
     const GyReader<BUF> g(a.gy, gy_plane<BLK>(a) * a.nz);
@@ -1175,6 +1242,20 @@ __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
     }
 }
 
+__device__ __forceinline__ bool zs_blocked(const ZsArgs& a)
+{
+    return a.b1count ? blocked_layout(a.b1count, (uint64_t)(a.nx * a.ny * a.nz)) : a.blk;
+}
+
+template <bool BUF>
+__global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
+{
+    if (zs_blocked(a))
+        interp_own<BUF, true>(a);
+    else
+        interp_own<BUF, false>(a);
+}
+
 // Which waves of k_interp_own a block of k_interp_far takes.  Searches of
 // voxels in the same (y, x) column and nearby planes read the same y-pass
 // lines, so where a plane holds whole waves (nx ny a multiple of 256) a block
@@ -1215,13 +1296,16 @@ __device__ __forceinline__ int64_t far_wave(const FarMap& f, int64_t nz, int64_t
 // The block's flagged voxels are listed in LDS (block-wide prefix sum of the
 // word popcounts) and dealt one per thread; lists longer than the LDS window
 // go in several rounds.
-template <bool BUF, bool BLK>
+constexpr int FAR_LIST = 1024;
+
+template <bool BUF>
 __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords, FarMap fm)
 {
-    constexpr int L = 1024;
+    constexpr int L = FAR_LIST;
     __shared__ int64_t list[L];
     __shared__ int wsum[4];
-    const int64_t plane = a.nx * a.ny, gplane = gy_plane<BLK>(a);
+    const bool blk = zs_blocked(a);
+    const int64_t plane = a.nx * a.ny, gplane = blk ? gy_plane<true>(a) : gy_plane<false>(a);
     const GyReader<BUF> g(a.gy, gplane * a.nz);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t grp = far_wave(fm, a.nz, nwords / 4, tid >> 2); // wave of k_interp_own
@@ -1269,7 +1353,8 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords, Fa
             const uint32_t w = a.w1[i];
             const float xv = a.xq[i];
             int z;
-            const int64_t jg = BUF ? (int64_t)gy_index32<BLK>(a, (uint32_t)i, z) : gy_index<BLK>(a, i);
+            const int64_t jg = BUF ? (int64_t)(blk ? gy_index32<true>(a, (uint32_t)i, z) : gy_index32<false>(a, (uint32_t)i, z))
+                                   : (blk ? gy_index<true>(a, i) : gy_index<false>(a, i));
             if (!BUF)
                 z = (int)(i / plane);
             const uint32_t d2 = zsearch<BUF>(g, jg, gplane, z, (int)a.nz);
@@ -1280,10 +1365,10 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords, Fa
     }
 }
 
-template <bool BUF, bool BLK>
+template <bool BUF>
 static hipError_t launch_interp_search_t(const ZsArgs& a, int64_t blocks, hipStream_t s)
 {
-    const hipError_t e = launch_checked(k_interp_own<BUF, BLK>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const hipError_t e = launch_checked(k_interp_own<BUF>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     if (e != hipSuccess)
         return e;
     const int64_t nwords = blocks * 16; // flag_bytes(n) / 8
@@ -1297,7 +1382,7 @@ static hipError_t launch_interp_search_t(const ZsArgs& a, int64_t blocks, hipStr
         fm.ncx = ((fm.zb + FAR_ZC - 1) / FAR_ZC + 7) / 8;
         grid = 8 * fm.pb * fm.ncx * FAR_ZC;
     }
-    return launch_checked(k_interp_far<BUF, BLK>, dim3((unsigned)grid), dim3(256), 0, s, a, nwords, fm);
+    return launch_checked(k_interp_far<BUF>, dim3((unsigned)grid), dim3(256), 0, s, a, nwords, fm);
 }
 
 static hipError_t launch_interp_search(const ZsArgs& a, bool force_wide, hipStream_t s)
@@ -1310,9 +1395,7 @@ static hipError_t launch_interp_search(const ZsArgs& a, bool force_wide, hipStre
         return hipErrorInvalidValue;
     // buffer loads by 32-bit byte offset while gy (natural or blocked) stays below 2^31 bytes
     const bool buf = word_capacity(a.nz, a.ny, a.nx) < ((int64_t)1 << 29) && !force_wide;
-    if (buf)
-        return a.blk ? launch_interp_search_t<true, true>(a, blocks, s) : launch_interp_search_t<true, false>(a, blocks, s);
-    return a.blk ? launch_interp_search_t<false, true>(a, blocks, s) : launch_interp_search_t<false, false>(a, blocks, s);
+    return buf ? launch_interp_search_t<true>(a, blocks, s) : launch_interp_search_t<false>(a, blocks, s);
 }
 
 // --------------------------------------------------------- envelope pass
@@ -1377,6 +1460,64 @@ __global__ __launch_bounds__(1024) void k_env_window(EnvArgs a)
             }
             a.w[base + (int64_t)r * stride + c] = best;
         }
+    }
+}
+
+// Direct outward search for short owner distances: one thread per voxel,
+// 256 consecutive voxels of one x-line per workgroup, the candidates read
+// straight from the pass input (the lines a voxel's search reads are the
+// neighbouring workgroups' own lines, so the caches serve most of them).
+// Every voxel of the field works at once, whatever the number of column
+// tiles: the choice for passes whose tiles are too few to fill the GPU.  Same
+// order and tie rule as k_env_window; four offsets per round with all eight
+// loads in flight.
+template <int AXIS>
+__global__ __launch_bounds__(256) void k_env_direct(EnvArgs a)
+{
+    if (a.gate && *a.gate == 0u)
+        return; // gated pass not needed (uniform over the grid)
+    const int64_t n = (AXIS == 1) ? a.ny : a.nz;
+    const int64_t stride = (AXIS == 1) ? a.nx : a.nx * a.ny;
+    const int64_t nxb = (a.nx + 255) >> 8;
+    const uint64_t units = (uint64_t)(a.nz * a.ny * nxb);
+    for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t line = (int64_t)(u / (uint64_t)nxb), xb = (int64_t)(u % (uint64_t)nxb);
+        const int64_t x = xb * 256 + threadIdx.x;
+        if (x >= a.nx)
+            continue;
+        const int64_t p = (AXIS == 1) ? line % a.ny : line / a.ny; // position along the pass axis
+        const int64_t i = line * a.nx + x;
+        uint32_t best = a.win[i];
+        bool done = false;
+        for (int64_t d0 = 1; d0 < n && !done; d0 += 4) {
+            uint32_t lo[4], hi[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t d = d0 + k;
+                lo[k] = (p - d >= 0) ? a.win[i - d * stride] : QAI_WORD_INF;
+                hi[k] = (p + d < n) ? a.win[i + d * stride] : QAI_WORD_INF;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t d = d0 + k;
+                const uint32_t d2s = (uint32_t)d * (uint32_t)d << 2;
+                if (done || d >= n || d2s > (best | 3u) || (p - d < 0 && p + d >= n)) {
+                    done = true;
+                    continue;
+                }
+                if (p - d >= 0) {
+                    const uint32_t cand = word_add(lo[k], d2s);
+                    if ((cand >> 2) <= (best >> 2))
+                        best = cand;
+                }
+                if (p + d < n) {
+                    const uint32_t cand = word_add(hi[k], d2s);
+                    if ((cand >> 2) < (best >> 2))
+                        best = cand;
+                }
+            }
+        }
+        a.w[i] = best;
     }
 }
 
@@ -2212,11 +2353,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void* p, uint3
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int AXIS, int C, int WPB, bool BLK>
-__global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
+__device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ring, uint32_t* stage)
 {
     static_assert(!BLK || AXIS == 1, "blocked output is for the y pass");
-    __shared__ uint32_t ring[WPB * C * 64];
-    __shared__ __align__(16) uint32_t stage[BLK ? WPB * 64 * 4 : 4];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     uint32_t* const rl = ring + wv * C * 64 + lane;
@@ -2457,6 +2596,27 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
     }
 }
 
+template <int AXIS, int C, int WPB, bool BLK>
+__global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
+{
+    __shared__ uint32_t ring[WPB * C * 64];
+    __shared__ __align__(16) uint32_t stage[BLK ? WPB * 64 * 4 : 4];
+    env_lane2<AXIS, C, WPB, BLK>(a, hb, ring, stage);
+}
+
+// The y pass ahead of the needed-voxel search: its output layout chosen on
+// the device (blocked_layout), from the first seed pass's B1 estimate.
+template <int C, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_env_lane2_y(EnvArgs a, int hb, const unsigned long long* b1count)
+{
+    __shared__ uint32_t ring[WPB * C * 64];
+    __shared__ __align__(16) uint32_t stage[WPB * 64 * 4];
+    if (blocked_layout(b1count, (uint64_t)(a.nx * a.ny * a.nz)))
+        env_lane2<1, C, WPB, true>(a, hb, ring, stage);
+    else
+        env_lane2<1, C, WPB, false>(a, hb, ring, stage);
+}
+
 __global__ void k_clear(uint32_t* p, int n)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2514,36 +2674,46 @@ static size_t slab_bytes(int64_t nx, int ty, int rows, int planes)
     return ring + (size_t)ty * nch * (64 + 8 + 4) + 64;
 }
 
-template <int MODE, int V>
+template <int MODE, int V, int P = 1, int WPB = 8>
 static hipError_t launch_seed_lane_t(const SeedArgs& in, int tz, hipStream_t s)
 {
     const bool taps = (MODE == 0) ? (in.tq || in.tb1 || in.tsb) : (in.ts || in.td1 || in.tb2);
-    constexpr int WPB = 8;
+    constexpr int LP = WPB / P;
     constexpr int VW4 = (V % 4 == 0) ? 4 : 1, VW2 = (V % 2 == 0) ? 2 : 1;
+    if (in.nx > 64 * V * P)
+        return hipErrorInvalidValue;
     SlabArgs A;
     A.s = in;
-    A.ty = WPB;
-    A.rows = WPB + 2;
+    A.ty = LP;
+    A.rows = LP + 2;
     A.planes = 3;
     A.tz = tz;
-    A.nby = (in.ny + WPB - 1) / WPB;
+    A.nby = (in.ny + LP - 1) / LP;
     A.nbz = (in.nz + tz - 1) / tz;
     const uint32_t grid = grid_cap((uint64_t)(A.nby * A.nbz), 1u << 20);
     const uintptr_t al = (uintptr_t)((MODE == 0) ? (const void*)in.xq : (const void*)in.w1) | (uintptr_t)in.wout;
     const dim3 g(grid), b(64 * WPB);
     if (taps)
-        return launch_checked(k_seed_lane<MODE, V, WPB, 1, true>, g, b, 0, s, A);
+        return launch_checked(k_seed_lane<MODE, V, WPB, 1, true, P>, g, b, 0, s, A);
     else if (V % 4 == 0 && in.nx % 4 == 0 && al % 16 == 0)
-        return launch_checked(k_seed_lane<MODE, V, WPB, VW4, false>, g, b, 0, s, A);
+        return launch_checked(k_seed_lane<MODE, V, WPB, VW4, false, P>, g, b, 0, s, A);
     else if (V % 2 == 0 && in.nx % 2 == 0 && al % 8 == 0)
-        return launch_checked(k_seed_lane<MODE, V, WPB, VW2, false>, g, b, 0, s, A);
+        return launch_checked(k_seed_lane<MODE, V, WPB, VW2, false, P>, g, b, 0, s, A);
     else
-        return launch_checked(k_seed_lane<MODE, V, WPB, 1, false>, g, b, 0, s, A);
+        return launch_checked(k_seed_lane<MODE, V, WPB, 1, false, P>, g, b, 0, s, A);
 }
 
 template <int MODE>
 static hipError_t launch_seed_lane(const SeedArgs& in, int tz, hipStream_t s)
 {
+    // lines of 513..4096 voxels: two, four or eight waves per line (eight in
+    // workgroups of sixteen waves: two lines each)
+    if (in.nx > 2048)
+        return launch_seed_lane_t<MODE, 8, 8, 16>(in, tz, s);
+    if (in.nx > 1024)
+        return launch_seed_lane_t<MODE, 8, 4>(in, tz, s);
+    if (in.nx > 512)
+        return launch_seed_lane_t<MODE, 8, 2>(in, tz, s);
     switch ((int)((in.nx + 63) / 64)) {
     case 1: return launch_seed_lane_t<MODE, 1>(in, tz, s);
     case 2: return launch_seed_lane_t<MODE, 2>(in, tz, s);
@@ -2556,39 +2726,50 @@ static hipError_t launch_seed_lane(const SeedArgs& in, int tz, hipStream_t s)
     }
 }
 
-// Step A from coded indices (k_seed_lane mode 2): lines of at most 512
-// voxels whose 64 lanes each hold a whole share of one 32-voxel segment.
+// Step A from coded indices (k_seed_lane mode 2): lines whose lanes each hold
+// a whole share of one 32-voxel segment: up to 512 voxels with ceil(nx / 64)
+// dividing 32, and 513..2048 voxels (eight voxels per lane, two or four waves
+// per line; eight waves would leave the decode too few registers).
+constexpr int64_t kCodedSeedMaxX = 2048;
 bool coded_seed_supported(int64_t nx)
 {
     const int64_t v = (nx + 63) / 64;
-    return nx <= 512 && (v == 1 || v == 2 || v == 4 || v == 8);
+    return (nx <= 512 && (v == 1 || v == 2 || v == 4 || v == 8)) || (nx > 512 && nx <= kCodedSeedMaxX);
 }
 
-template <int V>
+template <int V, int P = 1, int WPB = 8>
 static hipError_t launch_seed_coded_t(const SeedArgs& in, int tz, hipStream_t s)
 {
-    constexpr int WPB = 8;
+    constexpr int LP = WPB / P;
     constexpr int VW4 = (V % 4 == 0) ? 4 : 1, VW2 = (V % 2 == 0) ? 2 : 1;
+    if (in.nx > 64 * V * P)
+        return hipErrorInvalidValue;
     SlabArgs A;
     A.s = in;
-    A.ty = WPB;
-    A.rows = WPB + 2;
+    A.ty = LP;
+    A.rows = LP + 2;
     A.planes = 3;
     A.tz = tz;
-    A.nby = (in.ny + WPB - 1) / WPB;
+    A.nby = (in.ny + LP - 1) / LP;
     A.nbz = (in.nz + tz - 1) / tz;
     const uint32_t grid = grid_cap((uint64_t)(A.nby * A.nbz), 1u << 20);
     const uintptr_t al = (uintptr_t)in.xout | (uintptr_t)in.wout;
     const dim3 g(grid), b(64 * WPB);
     if (V % 4 == 0 && in.nx % 4 == 0 && al % 16 == 0)
-        return launch_checked(k_seed_lane<2, V, WPB, VW4, false>, g, b, 0, s, A);
+        return launch_checked(k_seed_lane<2, V, WPB, VW4, false, P>, g, b, 0, s, A);
     if (V % 2 == 0 && in.nx % 2 == 0 && al % 8 == 0)
-        return launch_checked(k_seed_lane<2, V, WPB, VW2, false>, g, b, 0, s, A);
-    return launch_checked(k_seed_lane<2, V, WPB, 1, false>, g, b, 0, s, A);
+        return launch_checked(k_seed_lane<2, V, WPB, VW2, false, P>, g, b, 0, s, A);
+    return launch_checked(k_seed_lane<2, V, WPB, 1, false, P>, g, b, 0, s, A);
 }
 
 hipError_t launch_seed_coded(const SeedArgs& in, int tz, hipStream_t s)
 {
+    if (in.nx > kCodedSeedMaxX)
+        return hipErrorInvalidValue;
+    if (in.nx > 1024)
+        return launch_seed_coded_t<8, 4>(in, tz, s);
+    if (in.nx > 512)
+        return launch_seed_coded_t<8, 2>(in, tz, s);
     switch ((int)((in.nx + 63) / 64)) {
     case 1: return launch_seed_coded_t<1>(in, tz, s);
     case 2: return launch_seed_coded_t<2>(in, tz, s);
@@ -2602,7 +2783,7 @@ hipError_t launch_seed(int mode, const SeedArgs& in, hipStream_t s, int want_ty,
 {
     if (want_ty < 0)
         return launch_seed_lines(mode, in, s); // one x-line per wave, neighbours through the caches
-    if (in.nx <= 512 && want_ty <= 0) {
+    if (in.nx <= kSeedLaneMaxX && want_ty <= 0) {
         const int tz = in.nz > 1 ? (want_tz > 0 ? want_tz : 16) : 1;
         return mode == 0 ? launch_seed_lane<0>(in, tz, s) : launch_seed_lane<1>(in, tz, s);
     }
@@ -2787,6 +2968,16 @@ static hipError_t launch_lane2_t(EnvArgs a, int hb, hipStream_t s)
     const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
     return launch_checked(k_env_lane2<AXIS, 32, WPB, BLK>, dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a,
                        hb);
+}
+
+static hipError_t launch_lane2_y(EnvArgs a, int hb, const unsigned long long* b1count, hipStream_t s)
+{
+    constexpr int WPB = 4;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    a.ntiles = (uint64_t)(nxb * a.nz);
+    const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
+    return launch_checked(k_env_lane2_y<32, WPB>, dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a, hb,
+                          b1count);
 }
 
 template <int AXIS>
@@ -3028,6 +3219,12 @@ hipError_t launch_env(int axis, EnvArgs a, const Tuning& t, hipStream_t s)
     }
     if (t.env_algo[axis] == 2 && n <= 64 * 32)
         return launch_band2(axis, a, t, s);
+    if (t.env_algo[axis] == 5) {
+        const uint64_t units = (uint64_t)(a.nz * a.ny * ((a.nx + 255) >> 8));
+        const dim3 grid(grid_cap(units, 1u << 18)), blk(256);
+        return axis == 1 ? launch_checked(k_env_direct<1>, grid, blk, 0, s, a)
+                         : launch_checked(k_env_direct<2>, grid, blk, 0, s, a);
+    }
     if (t.env_algo[axis] == 4)
         return axis == 1 ? launch_swin_t<1>(a, s) : launch_swin_t<2>(a, s);
     if (t.env_algo[axis] == 3) {
@@ -3139,6 +3336,15 @@ static SeedArgs seed_args(const Plan1& p)
     return sa;
 }
 
+// A 3-D field with both passes of the first EDT on automatic takes them as
+// one search over (y, z) (k_edt1_yz); its seed pass (k_seed_lane) then
+// estimates the B1 count, which the later passes read on the device.
+static bool fused_edt1(const Plan1& p, const Tuning& t, const Tuning& t_in)
+{
+    return p.nz > 1 && p.ny > 1 && p.nx % 4 == 0 && p.nx <= 512 && t.seed_ty == 0 && t_in.edt1_algo[1] < 0 &&
+           t_in.edt1_algo[2] < 0;
+}
+
 // Steps A and B (and the status words): afterwards the first EDT's final
 // words lie in word buffer *w1 (0, 1 or 2).
 hipError_t run_part1(Plan1& p, const Tuning& t_in, hipStream_t s, int* w1)
@@ -3155,8 +3361,7 @@ hipError_t run_part1(Plan1& p, const Tuning& t_in, hipStream_t s, int* w1)
     // EDT on automatic takes them as one search over (y, z) (k_edt1_yz), the
     // separable passes gated behind it; the final words land in buffer 0
     // either way
-    const bool yz = p.nz > 1 && p.ny > 1 && p.nx % 4 == 0 && p.nx <= 512 && t.seed_ty == 0 &&
-                    t_in.edt1_algo[1] < 0 && t_in.edt1_algo[2] < 0; // seed pass: k_seed_lane (counts B1)
+    const bool yz = fused_edt1(p, t, t_in);
     unsigned long long* const b1count = (unsigned long long*)(p.status + QAI_B1_WORD);
     sa.b1count = yz ? b1count : nullptr;
     int cur = yz ? 1 : 0;
@@ -3262,22 +3467,28 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
     prof_end(s);
 
     // remaining passes of step D; without taps, a 3-D field's last pass runs
-    // only where step E needs it (the needed-voxel search), and the y pass
-    // hands it its result in the blocked layout when the per-lane envelope
-    // runs it
+    // only where step E needs it (the needed-voxel search).  When the
+    // per-lane envelope runs the y pass ahead of it, the y pass hands its
+    // result over in the layout blocked_layout picks from the B1 estimate
+    // (blocked where there is no estimate)
     const qai_taps& tp = p.taps;
     const bool any_tap = tp.q || tp.b1 || tp.sb || tp.s || tp.d1sq || tp.b2 || tp.d2sq || tp.w;
     const bool aligned = (((uintptr_t)buf[w1] | (uintptr_t)p.xq | (uintptr_t)p.out) & 15u) == 0;
     const bool search = p.nz > 1 && !any_tap && t_in.env_algo[2] < 0 && p.flags && aligned;
     bool blk = false;
+    const unsigned long long* b1est = nullptr;
     if (p.ny > 1) {
         const int nx2 = (c2 == o0) ? o1 : o0;
         ea.win = buf[c2];
         ea.w = buf[nx2];
         int hb = 0;
         blk = search && t.env_algo[1] == 3 && lane2_geometry(1, ea, hb);
+        if (blk && fused_edt1(p, t, t_in))
+            b1est = (const unsigned long long*)(p.status + QAI_B1_WORD);
         prof_begin("edt2_y", s);
-        if (blk)
+        if (b1est)
+            QAI_TRY(launch_lane2_y(ea, hb, b1est, s));
+        else if (blk)
             QAI_TRY((launch_lane2_t<1, true>(ea, hb, s)));
         else
             QAI_TRY(launch_env(1, ea, t, s));
@@ -3287,7 +3498,8 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
     if (search) {
         // last pass of step D only at needed voxels, fused with step E
         const int nx2 = (c2 == o0) ? o1 : o0;
-        ZsArgs za = {buf[w1], buf[c2], buf[nx2], p.xq, p.out, p.flags, p.nx, p.ny, p.nz, p.eta * p.eb, p.power, blk};
+        ZsArgs za = {buf[w1], buf[c2], buf[nx2], p.xq, p.out, p.flags, p.nx, p.ny, p.nz, p.eta * p.eb, p.power, blk,
+                     b1est};
         prof_begin("edt2_z_interp", s);
         QAI_TRY(launch_interp_search(za, t.force_wide != 0, s));
         prof_end(s);

@@ -30,9 +30,29 @@ std::map<std::array<int64_t, 3>, Tuning> g_cache;
 
 std::array<int64_t, 3> key_of(const int64_t d[3]) { return {d[0], d[1], d[2]}; }
 
+// The y-pass variants with the per-voxel direct search (algorithm 5) for a
+// field whose y pass has fewer than 256 tiles of 64 columns; none otherwise.
+std::vector<Tuning> few_tile_variants(const Tuning& base, int64_t nz, int64_t ny, int64_t nx)
+{
+    std::vector<Tuning> out;
+    if (ny <= 1 || ((nx + 63) / 64) * nz >= 256)
+        return out;
+    const int e1s[2] = {-1, 5}, e2s[2] = {-1, 5};
+    for (int a : e1s)
+        for (int b : e2s) {
+            if (a != 5 && b != 5)
+                continue;
+            Tuning t = base;
+            t.edt1_algo[1] = a;
+            t.env_algo[1] = b;
+            out.push_back(t);
+        }
+    return out;
+}
+
 // Round 1: pass algorithms of both EDTs (automatic, the streaming kernel of
 // each EDT, the windowed search) times the seed variants.
-std::vector<Tuning> round1(const Tuning& base, int64_t nx)
+std::vector<Tuning> round1(const Tuning& base, int64_t nz, int64_t ny, int64_t nx)
 {
     std::vector<Tuning> out;
     const int e1s[3] = {-1, 4, 1}, e2s[3] = {-1, 3, 1};
@@ -40,8 +60,8 @@ std::vector<Tuning> round1(const Tuning& base, int64_t nx)
     for (int a : e1s)
         for (int b : e2s)
             for (auto& sd : seeds) {
-                if (sd[0] == 0 && nx > 512)
-                    continue; // the register seed variant needs lines of <= 512 voxels
+                if (sd[0] == 0 && nx > kSeedLaneMaxX)
+                    continue; // the register seed variant's longest line
                 Tuning t = base;
                 for (int k = 1; k < 3; ++k) {
                     t.edt1_algo[k] = a;
@@ -51,6 +71,18 @@ std::vector<Tuning> round1(const Tuning& base, int64_t nx)
                 t.seed_tz = sd[1];
                 out.push_back(t);
             }
+    // a y pass with few column tiles (a 2-D field): also the per-voxel direct
+    // search for either EDT's y pass, the one choice that fills the GPU there
+    for (const Tuning& t0 : few_tile_variants(base, nz, ny, nx)) {
+        for (auto& sd : seeds) {
+            if (sd[0] == 0 && nx > kSeedLaneMaxX)
+                continue;
+            Tuning t = t0;
+            t.seed_ty = sd[0];
+            t.seed_tz = sd[1];
+            out.push_back(t);
+        }
+    }
     return out;
 }
 
@@ -134,7 +166,7 @@ hipError_t tune_field(Plan1& p, const Tuning& base, hipStream_t s, Tuning& best,
     int timed = 0;
     for (int round = 0; round < 2 && e == hipSuccess; ++round) {
         const std::vector<Tuning> cands =
-            round == 0 ? round1(base, p.nx) : round2(best, p.nz, p.ny, p.nx);
+            round == 0 ? round1(base, p.nz, p.ny, p.nx) : round2(best, p.nz, p.ny, p.nx);
         for (const Tuning& t : cands) {
             float ms = 0.0f;
             if ((e = time_run(p, t, s, a, b, ms)) != hipSuccess)
@@ -179,6 +211,8 @@ hipError_t refine_field(Plan1& p, const Tuning& shape_best, hipStream_t s, Tunin
             }
             cands.push_back(t);
         }
+    for (const Tuning& t : few_tile_variants(shape_best, p.nz, p.ny, p.nx))
+        cands.push_back(t);
     float best_ms = 1e30f;
     best = shape_best;
     for (const Tuning& t : cands) {

@@ -2,9 +2,10 @@
 decoder reproduces the decompressed field bit for bit, the fused pass (the
 first seed pass decodes the lines it reads and writes x' into out) gives
 qai_mitigate_ex's result on that field bit for bit, for every supported line
-geometry (ceil(nx/64) in {1, 2, 4, 8}), ragged last segments, and the shapes
-that decode first; the indices are checked against the oracle's decoder and
-the output against the oracle."""
+geometry (ceil(nx/64) in {1, 2, 4, 8}; lines of 513..2048 voxels over two or
+four waves), ragged last segments, and the shapes that decode first; the
+indices are checked against the oracle's decoder and the output against the
+oracle."""
 import numpy as np
 import pytest
 import torch
@@ -17,7 +18,7 @@ from paper_2602_20097_amd import synth
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(24, 40, 64), (20, 30, 128), (16, 24, 256), (12, 20, 512), (8, 9, 70), (5, 7, 100), (10, 20, 384),
-          (1, 100, 300), (1, 1, 90), (3, 40, 600)]
+          (1, 100, 300), (1, 1, 90), (3, 40, 600), (4, 9, 1024), (3, 5, 1500), (2, 3, 2100)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)

@@ -158,11 +158,13 @@ def test_headline_512_full_parity():
     assert np.abs(g["out"].astype(np.float64) - x32).max() <= (1 + 0.9) * eb * (1 + 1e-6)
 
 
-@pytest.mark.parametrize("shape", [(1, 40, 2000), (5, 7, 1100), (3, 9, 600), (1, 3, 4099)])
+@pytest.mark.parametrize("shape", [(1, 40, 2000), (5, 7, 1100), (3, 9, 600), (4, 10, 1024), (3, 5, 2048),
+                                   (2, 6, 3600), (1, 9, 4096), (1, 3, 4099)])
 def test_long_lines(shape):
-    """x-lines longer than 512 voxels: the seed passes split each line over
-    several wavefronts (default) or keep it in one (explicit rows per block);
-    both agree with the oracle."""
+    """x-lines longer than 512 voxels: the register seed pass shares a line
+    between two (up to 1024 voxels), four (2048) or eight waves (4096), longer
+    lines go to the one-line-per-workgroup pass; explicit rows per block keep
+    a line in one wave of the LDS-slab pass; all agree with the oracle."""
     import paper_2602_20097_amd as qai
     x32, xq, q, eb = synth.quantize(synth.grf(shape, 3.0, 900 + sum(shape)), 2e-2)
     assert_parity(xq, eb, label=f"long lines {shape}")
@@ -191,6 +193,20 @@ def test_blocked_handoff_to_the_needed_voxel_search():
     finally:
         qai.set_tuning(None)
     assert qai.get_tuning() == base
+
+
+@pytest.mark.parametrize("rel,dense", [(1e-3, True), (2e-2, False)])
+def test_handoff_layout_follows_the_b1_density(rel, dense):
+    """On automatic passes the y pass of the second EDT picks the handoff
+    layout on the device from the first seed pass's B1 estimate: blocked where
+    B1 covers at least 90% of the field, natural elsewhere.  Fields on both
+    sides of that line (B1 checked with the oracle) match the tapped call and
+    the oracle."""
+    x32, xq, q, eb = synth.quantize(synth.grf((64, 128, 192), 3.0, 91), rel)
+    g, r = assert_parity(xq, eb, label=f"handoff rel {rel}")
+    needed = (r["s"] != 0) & (r["b1"] == 0)
+    assert needed.sum() > 500
+    assert (r["b1"].mean() >= 0.93) == dense and (r["b1"].mean() <= 0.87) == (not dense)
 
 
 def test_first_edt_beyond_the_search_disc():
@@ -239,7 +255,7 @@ def test_every_pass_algorithm_gives_the_same_transform():
             r = oracle.qai(xq, eb)
             # seed_rows: 0 register variant, 1..8 the LDS-slab variant (8: 512-thread
             # workgroups), -1 one line per wave
-            combos = [(a1, a2, 0) for a1 in (0, 1, 2, 4) for a2 in (0, 1, 2, 3, 4)] + \
+            combos = [(a1, a2, 0) for a1 in (0, 1, 2, 4, 5) for a2 in (0, 1, 2, 3, 4, 5)] + \
                 [(4, 3, r) for r in (8, 4, 2, 1, -1)]
             for a1, a2, rows in combos:
                 qai.set_tuning(edt1_algo=[a1, a1], edt2_algo=[a2, a2], seed_rows=rows)
