@@ -640,18 +640,15 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
         auto seg_of = [&](int64_t zz, int64_t yy, bool ok) -> int64_t {
             return ((ok ? zz : 0) * ny + (ok ? yy : 0)) * a.segs_row + cs;
         };
-        // step one: the meta word only (the first index comes with step two)
+        // step one: the segment head (meta word and first index)
         auto start = [&](int64_t zz, int64_t yy) -> Pend {
             Pend pd;
             pd.ok = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
-            pd.h.mt = a.cmeta[seg_of(zz, yy, pd.ok)];
+            pd.h = code_head(a.cbase, a.cmeta, seg_of(zz, yy, pd.ok));
             return pd;
         };
-        // step two: the first index and the payload words
-        auto fetch = [&](Pend& pd, int64_t zz, int64_t yy) {
-            pd.h.b0 = a.cbase[seg_of(zz, yy, pd.ok)];
-            code_words<V>(prs, pd.h, cp0, pd.w4);
-        };
+        // step two: the payload words
+        auto fetch = [&](Pend& pd) { code_words<V>(prs, pd.h, cp0, pd.w4); };
         // Loads go to valid addresses without branching: a line outside the
         // field reads line 0 and a group of words past the end of the line the
         // line's first group; keys() substitutes 0 for them (nx is a multiple
@@ -664,7 +661,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                 // the lane's V indices of the line, decoded at once (the
                 // prologue); the plane loop pipelines the steps (Pend)
                 Pend pd = start(zz, yy);
-                fetch(pd, zz, yy);
+                fetch(pd);
                 int32_t qv[V];
                 code_finish<V>(prs, pd.h, pd.w4, cp0, lane, qv);
 #pragma unroll
@@ -737,20 +734,12 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
             keys(hraw, hok, H);
             put(0, hrow, H);
         }
-        // coded input, decodes in flight: own line z0 + 2 with its payload
-        // words requested (DEEP) or its head, own line z0 + 3 with its head
-        // requested (DEEP), halo line z0 + 1 with its head requested (the plane
-        // loop keeps this shape and requests the other payload words when it
-        // decodes their lines).  DEEP for whole lines: pieces of long lines
-        // leave no room for the extra registers
-        constexpr bool DEEP = false;
-        Pend po{}, ph{}, pon{};
+        // coded input, decodes in flight: the segment heads of own line z0 + 2
+        // and halo line z0 + 1 requested (the plane loop keeps this shape and
+        // requests a line's payload words when it decodes the line)
+        Pend po{}, ph{};
         if constexpr (CODED) {
             po = start(z0 + 2, y);
-            if (DEEP) {
-                fetch(po, z0 + 2, y);
-                pon = start(z0 + 3, y);
-            }
             if (halo)
                 ph = start(z0 + 1, yh);
         } else {
@@ -934,10 +923,9 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                 }
                 if constexpr (CODED) {
                     int32_t qv[V];
-                    if (!DEEP)
-                        fetch(po, z + 2, y);
+                    fetch(po);
                     if (halo)
-                        fetch(ph, z + 1, yh);
+                        fetch(ph);
                     code_finish<V>(prs, po.h, po.w4, cp0, lane, qv);
 #pragma unroll
                     for (int j = 0; j < V; ++j)
@@ -959,13 +947,7 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
                     put(cur ^ 1, hrow, H);
                 }
                 if constexpr (CODED) {
-                    if (DEEP) {
-                        po = pon;
-                        fetch(po, z + 3, y);
-                        pon = start(z + 4, y);
-                    } else {
-                        po = start(z + 3, y);
-                    }
+                    po = start(z + 3, y);
                     if (halo)
                         ph = start(z + 2, yh);
                 } else {
@@ -1259,9 +1241,11 @@ __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
 // Which waves of k_interp_own a block of k_interp_far takes.  Searches of
 // voxels in the same (y, x) column and nearby planes read the same y-pass
 // lines, so where a plane holds whole waves (nx ny a multiple of 256) a block
-// takes 8 consecutive waves (whole rows) of 8 consecutive planes, and the
-// blocks on each XCD (block b runs on XCD b % 8) walk a column group through
-// a chunk of 64 planes in order: the lines they read stay in that XCD's L2.
+// takes 8 consecutive waves (whole rows) of FAR_ZG = 4 consecutive planes (8
+// planes: a few heavy blocks end the pass late; 2: the reuse falls off), and
+// the blocks on each XCD (block b runs on XCD b % 8) walk a column group
+// through a chunk of 64 planes in order: the lines they read stay in that
+// XCD's L2.
 // Chunk c of column group j goes to XCD (j + c) % 8, so every XCD takes
 // planes from the whole depth (the density of far voxels follows that of B2,
 // plane by plane); column groups are taken from both y faces inward, where B2
@@ -1269,10 +1253,10 @@ __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
 // first.  Otherwise a block takes 64 waves spaced gridDim.x apart.
 struct FarMap {
     int64_t wpp;      // waves per plane (0: the spaced mapping)
-    int64_t pb, zb;   // 8-wave groups per plane, 8-plane groups
-    int64_t ncx;      // chunks of FAR_ZC 8-plane groups per XCD and column group
+    int64_t pb, zb;   // 8-wave groups per plane, FAR_ZG-plane groups
+    int64_t ncx;      // chunks of FAR_ZC plane groups per XCD and column group
 };
-constexpr int FAR_ZC = 8;
+constexpr int FAR_ZG = 4, FAR_ZC = 64 / FAR_ZG;
 
 __device__ __forceinline__ int64_t far_wave(const FarMap& f, int64_t nz, int64_t nwaves, int lw)
 {
@@ -1287,12 +1271,14 @@ __device__ __forceinline__ int64_t far_wave(const FarMap& f, int64_t nz, int64_t
     const int64_t zb = zc * FAR_ZC + u % FAR_ZC;
     if (j >= f.pb || zb >= f.zb)
         return -1;
+    if ((lw >> 3) >= FAR_ZG)
+        return -1;
     const int64_t cg = (j & 1) ? f.pb - 1 - (j >> 1) : (j >> 1);
-    const int64_t z = zb * 8 + (lw >> 3), p = cg * 8 + (lw & 7);
+    const int64_t z = zb * FAR_ZG + (lw >> 3), p = cg * 8 + (lw & 7);
     return (z < nz && p < f.wpp) ? z * f.wpp + p : -1;
 }
 
-// A block takes the four flag words of 64 waves of k_interp_own (far_wave).
+// A block takes the four flag words of up to 64 waves of k_interp_own (far_wave).
 // The block's flagged voxels are listed in LDS (block-wide prefix sum of the
 // word popcounts) and dealt one per thread; lists longer than the LDS window
 // go in several rounds.
@@ -1378,7 +1364,7 @@ static hipError_t launch_interp_search_t(const ZsArgs& a, int64_t blocks, hipStr
     if (plane % 256 == 0) {
         fm.wpp = plane / 256;
         fm.pb = (fm.wpp + 7) / 8;
-        fm.zb = (a.nz + 7) / 8;
+        fm.zb = (a.nz + FAR_ZG - 1) / FAR_ZG;
         fm.ncx = ((fm.zb + FAR_ZC - 1) / FAR_ZC + 7) / 8;
         grid = 8 * fm.pb * fm.ncx * FAR_ZC;
     }
@@ -3067,6 +3053,14 @@ __global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide, cons
     const IDX nq = plane * nz / 4;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ntab = c_yz.n;
+    // With B1 below 90% of the field the searches would be long and often end
+    // beyond the disc: the pass stands down before it reads anything (block 0
+    // raises the gate of the separable passes)
+    if (*b1count * 10ull < (unsigned long long)(plane * nz) * 9ull) {
+        if (blockIdx.x == 0 && tid == 0)
+            atomicOr(wide, 1u);
+        return;
+    }
     bool unsettled = false;
     for (IDX q0 = (IDX)blockIdx.x * (256 * U); q0 < nq; q0 += (IDX)gridDim.x * (256 * U)) {
         uint4 c[U];
@@ -3077,16 +3071,10 @@ __global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide, cons
         }
         // once some block has raised *wide the separable passes recompute the
         // whole field: the rest of this pass is moot (what a block wrote before
-        // it stops is overwritten).  With B1 below 90% of the field the searches
-        // would be long and often end beyond the disc: the pass stands down at
-        // once (block 0 raises the flag).  Read with the quads, acted on at the
-        // list barrier.
-        if (tid == 0) {
-            const bool sparse = *b1count * 10ull < (unsigned long long)(plane * nz) * 9ull;
-            if (sparse && blockIdx.x == 0 && q0 == 0)
-                atomicOr(wide, 1u);
-            stop = sparse || __hip_atomic_load(wide, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-        }
+        // it stops is overwritten).  Read with the quads, acted on at the list
+        // barrier.
+        if (tid == 0)
+            stop = __hip_atomic_load(wide, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         uint64_t m[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
