@@ -29,6 +29,7 @@ STAGES = [
     (r"k_seed_(lane|seg|slab|xscan|lines)<1", "seed2_xscan"),
     (r"k_interp_(own|far)", "edt2_z_interp"),
     (r"k_edt1_yz", "edt1_yz"),
+    (r"k_env_lane2_y\b", "edt2_y"),
     (r"k_interp\b", "interp"),
     (r"k_copy", "copy_probe"),
     (r"k_clear", "clear"),
@@ -38,7 +39,7 @@ SEED2 = r"k_seed_(lane|seg|slab|xscan|lines)<1"
 
 
 # the sources of the plain pass's kernels (the ones the traffic figures cover)
-REV_SOURCES = ("qai_plain.hip", "qai_device.h")
+REV_SOURCES = ("qai_plain.hip", "qai_device.h", "qai_code.h")
 
 
 def kernel_rev():
