@@ -79,7 +79,11 @@ struct EnvArgs {
 // cleared with the status word: QAI_WIDE_WORD is raised when some voxel's
 // distance lies beyond the search disc (or the pass stands down), and the
 // 64-bit estimate of the B1 voxels from the seed pass sits at QAI_B1_WORD.
+// QAI_OVF_WORD is raised when the second EDT's y pass (per-lane envelope)
+// finds a column whose live window outgrows its ring; the banded pass then
+// recomputes the whole y pass (gated on the word).
 #define QAI_WIDE_WORD 16
+#define QAI_OVF_WORD 17
 #define QAI_B1_WORD 18
 #define QAI_HEADER_WORDS 20
 

@@ -766,9 +766,9 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
 #pragma unroll
                             for (int u = 0; u < VW; ++u)
                                 xv[u] = (float)(int32_t)(P1[j + u] ^ 0x80000000u) * a.two_eb;
-                            if (VW == 4)
+                            if constexpr (VW == 4)
                                 *(float4*)(xrow + j) = make_float4(xv[0], xv[1], xv[2], xv[3]);
-                            else if (VW == 2)
+                            else if constexpr (VW == 2)
                                 *(float2*)(xrow + j) = make_float2(xv[0], xv[1]);
                             else
                                 xrow[j] = xv[0];
@@ -1027,6 +1027,7 @@ struct ZsArgs {
     float eta_eb, power;
     bool blk;             // gy in the blocked layout [z][y/4][x][y%4] (else natural)
     const unsigned long long* b1count; // when set, the layout is chosen on the device (blocked_layout)
+    const uint32_t* ovf;  // when set and raised, the y pass was redone by the banded pass (natural layout)
 };
 
 // The y pass of the second EDT hands the needed-voxel search its words in the
@@ -1226,6 +1227,8 @@ __device__ __forceinline__ void interp_own(const ZsArgs& a)
 
 __device__ __forceinline__ bool zs_blocked(const ZsArgs& a)
 {
+    if (a.ovf && *a.ovf != 0u)
+        return false;
     return a.b1count ? blocked_layout(a.b1count, (uint64_t)(a.nx * a.ny * a.nz)) : a.blk;
 }
 
@@ -1718,6 +1721,8 @@ __global__ __launch_bounds__(1024) void k_env_band2(EnvArgs a, int lb)
     L.PREV = (int16_t*)(L.G + (size_t)L.colstride * Tx);
     L.NEXT = L.PREV + (size_t)L.colstride * Tx;
 
+    if (a.gate && *a.gate == 0u)
+        return; // gated pass not needed (uniform over the grid)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int b = lane & (B - 1);                      // band of this lane
@@ -2338,8 +2343,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void* p, uint3
 // single-word stores scattered over 64 rows.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// ovf_flag: when set, a wave with a column whose live window outgrew the
+// ring raises it and leaves the whole pass to the banded pass gated on it;
+// otherwise such columns take an exact outward search here.
 template <int AXIS, int C, int WPB, bool BLK>
-__device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ring, uint32_t* stage)
+__device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ring, uint32_t* stage,
+                                          uint32_t* ovf_flag = nullptr)
 {
     static_assert(!BLK || AXIS == 1, "blocked output is for the y pass");
     const int lane = threadIdx.x & 63;
@@ -2550,6 +2559,11 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
         const uint32_t* __restrict__ inb = a.win + tb;
         uint32_t* const outb = a.w + tbo;
         uint64_t om = __ballot(ovf && valid);
+        if (ovf_flag && om) {
+            if (lane == 0)
+                atomicOr(ovf_flag, 1u);
+            om = 0ull;
+        }
         while (om) {
             const int l = __ffsll((unsigned long long)om) - 1;
             om &= om - 1ull;
@@ -2591,16 +2605,18 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
 }
 
 // The y pass ahead of the needed-voxel search: its output layout chosen on
-// the device (blocked_layout), from the first seed pass's B1 estimate.
+// the device (blocked_layout) from the first seed pass's B1 estimate, blocked
+// where there is none (b1count null).
 template <int C, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_env_lane2_y(EnvArgs a, int hb, const unsigned long long* b1count)
+__global__ __launch_bounds__(64 * WPB) void k_env_lane2_y(EnvArgs a, int hb, const unsigned long long* b1count,
+                                                          uint32_t* ovf_flag)
 {
     __shared__ uint32_t ring[WPB * C * 64];
     __shared__ __align__(16) uint32_t stage[WPB * 64 * 4];
-    if (blocked_layout(b1count, (uint64_t)(a.nx * a.ny * a.nz)))
-        env_lane2<1, C, WPB, true>(a, hb, ring, stage);
+    if (!b1count || blocked_layout(b1count, (uint64_t)(a.nx * a.ny * a.nz)))
+        env_lane2<1, C, WPB, true>(a, hb, ring, stage, ovf_flag);
     else
-        env_lane2<1, C, WPB, false>(a, hb, ring, stage);
+        env_lane2<1, C, WPB, false>(a, hb, ring, stage, ovf_flag);
 }
 
 __global__ void k_clear(uint32_t* p, int n)
@@ -2887,7 +2903,9 @@ static hipError_t launch_band2(int axis, EnvArgs a, const Tuning& t, hipStream_t
     a.tx_log2 = txl;
     const int64_t nxb = (a.nx + (1 << txl) - 1) >> txl;
     a.ntiles = (uint64_t)(nxb * (axis == 1 ? a.nz : a.ny));
-    const uint32_t grid = grid_cap(a.ntiles, 1u << 20);
+    // a gated launch (usually not needed) keeps its grid small: every block
+    // starts only to read the gate
+    const uint32_t grid = grid_cap(a.ntiles, a.gate ? 2048u : (1u << 20));
     const int threads = (1 << lb) << txl;
     if (axis == 1)
         return launch_band2_m<1>(a, M, lb, lds, threads, grid, s);
@@ -2956,14 +2974,15 @@ static hipError_t launch_lane2_t(EnvArgs a, int hb, hipStream_t s)
                        hb);
 }
 
-static hipError_t launch_lane2_y(EnvArgs a, int hb, const unsigned long long* b1count, hipStream_t s)
+static hipError_t launch_lane2_y(EnvArgs a, int hb, const unsigned long long* b1count, uint32_t* ovf_flag,
+                                 hipStream_t s)
 {
     constexpr int WPB = 4;
     const int64_t nxb = (a.nx + 63) >> 6;
     a.ntiles = (uint64_t)(nxb * a.nz);
     const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
     return launch_checked(k_env_lane2_y<32, WPB>, dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a, hb,
-                          b1count);
+                          b1count, ovf_flag);
 }
 
 template <int AXIS>
@@ -3465,6 +3484,7 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
     const bool search = p.nz > 1 && !any_tap && t_in.env_algo[2] < 0 && p.flags && aligned;
     bool blk = false;
     const unsigned long long* b1est = nullptr;
+    uint32_t* ovf = nullptr;
     if (p.ny > 1) {
         const int nx2 = (c2 == o0) ? o1 : o0;
         ea.win = buf[c2];
@@ -3473,13 +3493,20 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
         blk = search && t.env_algo[1] == 3 && lane2_geometry(1, ea, hb);
         if (blk && fused_edt1(p, t, t_in))
             b1est = (const unsigned long long*)(p.status + QAI_B1_WORD);
+        // columns whose envelope outgrows the per-lane ring (sparse B2 over
+        // long x-lines) hand the pass to the banded pass, gated on a header word
+        if (blk && p.ny <= 64 * 32)
+            ovf = p.status + QAI_OVF_WORD;
         prof_begin("edt2_y", s);
-        if (b1est)
-            QAI_TRY(launch_lane2_y(ea, hb, b1est, s));
-        else if (blk)
-            QAI_TRY((launch_lane2_t<1, true>(ea, hb, s)));
+        if (blk)
+            QAI_TRY(launch_lane2_y(ea, hb, b1est, ovf, s));
         else
             QAI_TRY(launch_env(1, ea, t, s));
+        if (ovf) {
+            EnvArgs eg = ea;
+            eg.gate = ovf;
+            QAI_TRY(launch_band2(1, eg, t, s));
+        }
         prof_end(s);
         c2 = nx2;
     }
@@ -3487,7 +3514,7 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
         // last pass of step D only at needed voxels, fused with step E
         const int nx2 = (c2 == o0) ? o1 : o0;
         ZsArgs za = {buf[w1], buf[c2], buf[nx2], p.xq, p.out, p.flags, p.nx, p.ny, p.nz, p.eta * p.eb, p.power, blk,
-                     b1est};
+                     b1est, ovf};
         prof_begin("edt2_z_interp", s);
         QAI_TRY(launch_interp_search(za, t.force_wide != 0, s));
         prof_end(s);

@@ -51,21 +51,24 @@ std::vector<Tuning> few_tile_variants(const Tuning& base, int64_t nz, int64_t ny
 }
 
 // Round 1: pass algorithms of both EDTs (automatic, the streaming kernel of
-// each EDT, the windowed search) times the seed variants.
+// each EDT, the windowed search, the banded envelope for the second EDT's y
+// pass) times the seed variants.
 std::vector<Tuning> round1(const Tuning& base, int64_t nz, int64_t ny, int64_t nx)
 {
     std::vector<Tuning> out;
-    const int e1s[3] = {-1, 4, 1}, e2s[3] = {-1, 3, 1};
+    // second EDT (y, z): automatic, per-lane envelope, windowed search, and the
+    // banded envelope for the y pass ahead of the needed-voxel search
+    const int e1s[3] = {-1, 4, 1}, e2s[4][2] = {{-1, -1}, {3, 3}, {1, 1}, {2, -1}};
     const int seeds[3][2] = {{0, 16}, {0, 32}, {4, 16}};
     for (int a : e1s)
-        for (int b : e2s)
+        for (auto& b : e2s)
             for (auto& sd : seeds) {
                 if (sd[0] == 0 && nx > kSeedLaneMaxX)
                     continue; // the register seed variant's longest line
                 Tuning t = base;
                 for (int k = 1; k < 3; ++k) {
                     t.edt1_algo[k] = a;
-                    t.env_algo[k] = b;
+                    t.env_algo[k] = b[k - 1];
                 }
                 t.seed_ty = sd[0];
                 t.seed_tz = sd[1];
@@ -201,13 +204,13 @@ hipError_t refine_field(Plan1& p, const Tuning& shape_best, hipStream_t s, Tunin
     }
     std::vector<Tuning> cands;
     cands.push_back(shape_best);
-    const int e1s[2] = {-1, 1}, e2s[3] = {-1, 3, 1};
+    const int e1s[2] = {-1, 1}, e2s[4][2] = {{-1, -1}, {3, 3}, {1, 1}, {2, -1}};
     for (int x : e1s)
-        for (int y : e2s) {
+        for (auto& y : e2s) {
             Tuning t = shape_best;
             for (int k = 1; k < 3; ++k) {
                 t.edt1_algo[k] = x;
-                t.env_algo[k] = y;
+                t.env_algo[k] = y[k - 1];
             }
             cands.push_back(t);
         }

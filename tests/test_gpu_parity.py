@@ -319,3 +319,30 @@ def test_wide_index_variants(shape, rel):
     finally:
         qai.set_tuning(None)
     assert qai.get_tuning() == base
+
+
+@pytest.mark.parametrize("shape,rel", [((6, 200, 64), 2e-2), ((4, 300, 130), 3e-3), ((3, 513, 70), 2e-2),
+                                       ((5, 257, 96), 5e-3), ((64, 256, 192), 1e-3), ((2, 640, 64), 1e-2)])
+def test_tall_columns_with_few_tiles(shape, rel):
+    """y passes over tall columns with few column tiles (rows per plane not a
+    multiple of 4, sparse fields with long distances along y, and a dense one
+    that hands the blocked layout to the needed-voxel search): the untapped
+    call matches the tapped one bit for bit and both match the oracle."""
+    x32, xq, q, eb = synth.quantize(synth.grf(shape, 3.0, 31 + sum(shape)), rel)
+    assert_parity(xq, eb, label=f"tall columns {shape} rel {rel}")
+
+
+def test_envelope_ring_overflow_hands_the_y_pass_to_the_banded_pass():
+    """Sparse B2 over long x-lines: some column's live window outgrows the
+    per-lane envelope's ring in the second EDT's y pass, the pass raises the
+    header word and the banded pass (gated on it) redoes the whole y pass in
+    the natural layout, which the needed-voxel search then reads.  The output
+    matches the tapped call and the oracle."""
+    import paper_2602_20097_amd as qai
+    x32, xq, q, eb = synth.quantize(synth.grf((16, 128, 1024), 3.7, 77), 1.6e-4)
+    t = torch.from_numpy(xq).cuda()
+    ws = qai.new_workspace(t.shape)
+    qai.mitigate(t, eb, workspace=ws)
+    torch.cuda.synchronize()
+    assert int(ws[68:72].view(torch.int32).item()) != 0  # header word 17: the ring overflowed
+    assert_parity(xq, eb, label="ring overflow (16, 128, 1024)")
