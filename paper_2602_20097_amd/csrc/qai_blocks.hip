@@ -13,6 +13,11 @@
 //    E.  Both EDTs stay local: ghost voxels lie on the region's edge, so they
 //    are never sites.
 // The exact strategy is the whole-field pass (qai_mitigate_ex).
+// The blocks are independent between the exchanges, so their pipelines run
+// concurrently on four side streams (one per hardware queue of the process),
+// forked from and joined back to the caller's stream.
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "qai.h"
@@ -27,6 +32,59 @@ namespace {
 struct Box {
     int64_t o[3], e[3]; // origin and extent per axis (z, y, x)
 };
+
+// Side streams and fork/join events per device, created on first use and kept
+// for the process (default priority).  A call holds the mutex while it
+// enqueues, so concurrent calls never interleave their records and waits on
+// the shared events.
+constexpr int kSides = 4;
+struct Sides {
+    hipStream_t side[kSides] = {};
+    hipEvent_t fork = nullptr, join[kSides] = {};
+};
+std::mutex g_sides_mu;
+std::map<int, Sides> g_sides;
+
+hipError_t sides_for(int dev, Sides*& out)
+{
+    auto it = g_sides.find(dev);
+    if (it != g_sides.end()) {
+        out = &it->second;
+        return hipSuccess;
+    }
+    Sides sd;
+    hipError_t e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming);
+    for (int k = 0; k < kSides && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&sd.side[k], hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&sd.join[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess)
+        return e; // (what was created stays: a failed call is not retried here)
+    out = &g_sides.emplace(dev, sd).first->second;
+    return hipSuccess;
+}
+
+// the side streams wait for the work enqueued on s so far
+hipError_t fork_sides(const Sides& sd, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(sd.fork, s);
+    for (int k = 0; k < kSides && e == hipSuccess; ++k)
+        e = hipStreamWaitEvent(sd.side[k], sd.fork, 0);
+    return e;
+}
+
+// s waits for the work enqueued on the side streams
+hipError_t join_sides(const Sides& sd, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kSides && e == hipSuccess; ++k) {
+        e = hipEventRecord(sd.join[k], sd.side[k]);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(s, sd.join[k], 0);
+    }
+    return e;
+}
 
 void bounds(int64_t n, int k, int i, int64_t& o, int64_t& e)
 {
@@ -220,14 +278,20 @@ int qai_mitigate_blocks(const float* field, const int64_t dims[3], float eb, con
         if ((e = (expr)) != hipSuccess)                  \
             return fail_hip(e, "block pipeline launch"); \
     } while (0)
+    std::lock_guard<std::mutex> lk(qai::g_sides_mu);
+    qai::Sides* sd = nullptr;
+    QAI_BTRY(qai::sides_for(dev, sd));
     for (Blk& b : bl)
         QAI_BTRY(qai::copy_region(field, dims, b.reg, b.real, (void*)b.plan.xq, false, s));
+    QAI_BTRY(qai::fork_sides(*sd, s));
     if (!approx) {
-        for (Blk& b : bl)
-            QAI_BTRY(qai::run_plain(b.plan, b.tune, s));
+        for (size_t i = 0; i < bl.size(); ++i)
+            QAI_BTRY(qai::run_plain(bl[i].plan, bl[i].tune, sd->side[i % qai::kSides]));
+        QAI_BTRY(qai::join_sides(*sd, s));
     } else {
-        for (Blk& b : bl)
-            QAI_BTRY(qai::run_part1(b.plan, b.tune, s, &b.w1));
+        for (size_t i = 0; i < bl.size(); ++i)
+            QAI_BTRY(qai::run_part1(bl[i].plan, bl[i].tune, sd->side[i % qai::kSides], &bl[i].w1));
+        QAI_BTRY(qai::join_sides(*sd, s));
         // exchange: every block's own first-EDT words to the shared array ...
         for (Blk& b : bl) {
             uint32_t* bufs[3] = {b.plan.bufA, b.plan.bufB, b.plan.bufC};
@@ -238,8 +302,10 @@ int qai_mitigate_blocks(const float* field, const int64_t dims[3], float eb, con
             uint32_t* bufs[3] = {b.plan.bufA, b.plan.bufB, b.plan.bufC};
             QAI_BTRY(qai::copy_region(shared_words, dims, b.reg, b.real, bufs[b.w1], true, s));
         }
-        for (Blk& b : bl)
-            QAI_BTRY(qai::run_part2(b.plan, b.tune, s, b.w1));
+        QAI_BTRY(qai::fork_sides(*sd, s));
+        for (size_t i = 0; i < bl.size(); ++i)
+            QAI_BTRY(qai::run_part2(bl[i].plan, bl[i].tune, sd->side[i % qai::kSides], bl[i].w1));
+        QAI_BTRY(qai::join_sides(*sd, s));
     }
     for (Blk& b : bl)
         QAI_BTRY(qai::store_region(b.plan.out, b.reg, b.real, out, dims, s));
