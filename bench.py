@@ -73,6 +73,8 @@ STAGE_BYTES = {
     "interp": 16,         # read second-EDT words, first-EDT words, x'; write out
     "edt2_z_interp": 12,  # fused last pass: read first-EDT words, x'; write out (the z search reads the
                           # y-pass words only at the voxels whose weight needs d2, ~3% at 512^3)
+    "edt2_z_stream": 12,  # its streaming phase alone, on a side stream beside the y pass
+    "edt2_z_search": 0,   # its search phase: reads only at the voxels whose weight needs d2
     "clear": 0,
 }
 
@@ -222,6 +224,7 @@ def main():
             "copy_GBps": round(copy_gbps, 1),
             "stages_us": {k: round(v * 1e3, 1) for k, v in per_launch.items()},
             "stage_sum_ms": round(sum(per_launch.values()), 4),
+            "side_stream_stages": [k for k in per_launch if k == "edt2_z_stream"],
             "step_ms_median": round(step["median"], 4),
             "step_ms_trimmed_mean": round(step["trimmed_mean"], 4)},
     }

@@ -260,8 +260,11 @@ namespace {
 constexpr size_t kPartialOffset = 256; // FP64 partial sums of the adjoint reduction
 
 
+// side: run the streaming part of step E on the device's side stream
+// alongside the second EDT's y pass (qai::Aux); the allocation-free entry
+// point keeps every launch on the caller's stream
 int plain_checked(const float* field, const int64_t dims[3], float eb, const qai_params* params, void* ws,
-                  size_t ws_bytes, float* out, const qai_taps* taps, void* stream)
+                  size_t ws_bytes, float* out, const qai_taps* taps, void* stream, bool side)
 {
     int64_t n;
     int rc = check_dims(dims, &n);
@@ -300,6 +303,12 @@ int plain_checked(const float* field, const int64_t dims[3], float eb, const qai
     if (taps)
         pl.taps = *taps;
     const qai::Tuning t = tuning_for(dims);
+    std::unique_lock<std::mutex> lk;
+    if (side) {
+        if ((e = qai::aux_for(dev, pl.aux)) != hipSuccess)
+            return fail_hip(e, "side stream");
+        lk = std::unique_lock<std::mutex>(pl.aux->mu);
+    }
     e = qai::run_plain(pl, t, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail_hip(e, "kernel launch");
@@ -375,7 +384,7 @@ int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const q
                     size_t ws_bytes, float* out, const qai_taps* taps, void* stream)
 {
     g_err.clear();
-    return plain_checked(field, dims, eb, params, ws, ws_bytes, out, taps, stream);
+    return plain_checked(field, dims, eb, params, ws, ws_bytes, out, taps, stream, true);
 }
 
 int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out, void* stream)
@@ -394,7 +403,7 @@ int qai_mitigate(const float* field, const int64_t dims[3], float eb, float* out
     hipError_t e = hipMallocAsync(&ws, need, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail_hip(e, "hipMallocAsync");
-    rc = plain_checked(field, dims, eb, nullptr, ws, need, out, nullptr, stream);
+    rc = plain_checked(field, dims, eb, nullptr, ws, need, out, nullptr, stream, true);
     e = hipFreeAsync(ws, (hipStream_t)stream);
     if (rc == QAI_OK && e != hipSuccess)
         return fail_hip(e, "hipFreeAsync");
@@ -416,7 +425,7 @@ int qai_mitigate_noalloc(const float* field, const int64_t dims[3], float eb, co
     void* ws = nullptr;
     if ((rc = scratch_on_current_device(&ws)))
         return rc;
-    return plain_checked(field, dims, eb, params, ws, (size_t)QAI_NOALLOC_SCRATCH_BYTES, out, nullptr, stream);
+    return plain_checked(field, dims, eb, params, ws, (size_t)QAI_NOALLOC_SCRATCH_BYTES, out, nullptr, stream, false);
 }
 
 int qai_device_status(const void* ws, void* stream, uint32_t* flags)

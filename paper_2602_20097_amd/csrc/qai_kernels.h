@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <mutex>
 
 #include "qai.h"
 
@@ -155,6 +156,18 @@ hipError_t launch_seed_coded(const SeedArgs& in, int tz, hipStream_t s);
 // x' = 2 eb q of every voxel from the code (one wave per two segments)
 hipError_t launch_decode(const Coded& c, int64_t nz, int64_t ny, int64_t nx, float two_eb, float* xq, hipStream_t s);
 
+// A side stream and two events per device.  With one attached to a plan, the
+// streaming part of step E (every voxel whose weight does not need the second
+// EDT's z pass) runs on the side stream while the second EDT's y pass runs on
+// the caller's stream, ordered by the events.  The caller holds mu from the
+// plan's first launch to its last (the events are shared).
+struct Aux {
+    std::mutex mu;
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+hipError_t aux_for(int dev, Aux*& out);
+
 struct Plan1 {
     const Coded* coded;   // when set, the indices come from this code and x' is written to out
     const float* xq;
@@ -166,6 +179,7 @@ struct Plan1 {
     uint32_t* bufC;
     uint32_t* status;
     uint64_t* flags;      // fused final pass: one bit per voxel, see flag_bytes
+    Aux* aux;             // when set (mu held), the overlap described at Aux
     qai_taps taps;
     const uint32_t* w1_final;
     const uint32_t* w2_final;

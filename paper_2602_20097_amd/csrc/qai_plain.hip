@@ -12,8 +12,9 @@
 //                    step D.
 //   k_env_*          the y pass of step D, then either the z pass and
 //                    k_interp (step E), or, for a 3-D call without taps,
-//                    k_interp_own / k_interp_far: step E with the z pass
-//                    done only where the weight depends on it.
+//                    k_interp_own (or k_interp_pre, alongside the y pass) /
+//                    k_interp_far: step E with the z pass done only where
+//                    the weight depends on it.
 // No dense contraction exists on this path: the stencil and scan kernels are
 // bound by VALU issue, the envelope and search kernels by dependent latency,
 // the streaming ones by HBM.
@@ -22,6 +23,13 @@
 #include "qai_kernels.h"
 #include <algorithm>
 #include <type_traits>
+
+#define QAI_TRY(expr)                   \
+    do {                                \
+        hipError_t e_ = (expr);         \
+        if (e_ != hipSuccess)           \
+            return e_;                  \
+    } while (0)
 
 namespace qai {
 
@@ -1028,6 +1036,7 @@ struct ZsArgs {
     bool blk;             // gy in the blocked layout [z][y/4][x][y%4] (else natural)
     const unsigned long long* b1count; // when set, the layout is chosen on the device (blocked_layout)
     const uint32_t* ovf;  // when set and raised, the y pass was redone by the banded pass (natural layout)
+    const uint32_t* gx;   // k_interp_pre: the x-pass words of the second EDT (natural layout; w2 holds them)
 };
 
 // The y pass of the second EDT hands the needed-voxel search its words in the
@@ -1149,16 +1158,23 @@ __device__ __forceinline__ uint32_t zsearch(const GyReader<BUF>& g, int64_t i, i
 }
 
 // out at a needed voxel from its distance value d2 (QAI_WORD_INF: no B2)
-__device__ __forceinline__ float interp_at(const ZsArgs& a, int64_t i, uint32_t w1w, float xv, uint32_t d2)
+__device__ __forceinline__ float interp_val(const ZsArgs& a, uint32_t w1w, float xv, uint32_t d2)
 {
     const bool none2 = d2 == QAI_WORD_INF;
-    a.w2[i] = none2 ? QAI_WORD_INF : (d2 << 2);
     const float wt = idw_weight(word_d2(w1w), false, none2 ? 0u : d2, none2, a.power);
     return fmaf(wt, (float)word_sign(w1w) * a.eta_eb, xv);
 }
+// the same, with the distance word stored to w2
+__device__ __forceinline__ float interp_at(const ZsArgs& a, int64_t i, uint32_t w1w, float xv, uint32_t d2)
+{
+    a.w2[i] = d2 == QAI_WORD_INF ? QAI_WORD_INF : (d2 << 2);
+    return interp_val(a, w1w, xv, d2);
+}
 
 // step E where the weight does not need the search; false where it does (out
-// then keeps x' for the second phase)
+// then keeps x' for the second phase).  W2: store the distance word of a
+// voxel on B2 (without it, w2 must already hold 0 there)
+template <bool W2>
 __device__ __forceinline__ bool interp_near(const ZsArgs& a, int64_t i, uint32_t w, float x, uint32_t g, float& o)
 {
     const int s = word_sign(w);
@@ -1167,7 +1183,7 @@ __device__ __forceinline__ bool interp_near(const ZsArgs& a, int64_t i, uint32_t
     } else if (word_d2(w) == 0u) {
         o = fmaf(1.0f, (float)s * a.eta_eb, x); // on B1: w = 1
     } else if (g == 0u) {
-        o = interp_at(a, i, w, x, 0u);          // on B2: w = 0
+        o = W2 ? interp_at(a, i, w, x, 0u) : interp_val(a, w, x, 0u); // on B2: w = 0
     } else {
         o = x;
         return false;
@@ -1175,11 +1191,17 @@ __device__ __forceinline__ bool interp_near(const ZsArgs& a, int64_t i, uint32_t
     return true;
 }
 
-template <bool BUF, bool BLK>
+// PRE: the voxel's own word comes from the x pass (a.gx, natural layout)
+// instead of the y pass.  A voxel lies on B2 exactly where its x-pass word is
+// 0 (the voxel is itself a site), which is where the y-pass word is 0, so the
+// flags and outputs are those of the y-pass form; the y pass may still be
+// running.  The x-pass words hold 0 at B2 sites already, so w2 (the same
+// buffer) is not written.
+template <bool BUF, bool BLK, bool PRE = false>
 __device__ __forceinline__ void interp_own(const ZsArgs& a)
 {
     const int64_t n = a.nx * a.ny * a.nz;
-    const GyReader<BUF> g(a.gy, gy_plane<BLK>(a) * a.nz);
+    const GyReader<BUF> g(PRE ? a.gx : a.gy, PRE ? n : gy_plane<BLK>(a) * a.nz);
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     bool far[4] = {false, false, false, false};
     uint32_t w[4];
@@ -1202,13 +1224,14 @@ __device__ __forceinline__ void interp_own(const ZsArgs& a)
     for (int k = 0; k < 4; ++k) {
         const bool nd = word_sign(w[k]) != 0 && word_d2(w[k]) != 0u;
         int z;
-        const int64_t j = BUF ? (int64_t)gy_index32<BLK>(a, (uint32_t)min(i0 + k, n - 1), z)
-                              : gy_index<BLK>(a, min(i0 + k, n - 1));
+        const int64_t j = PRE   ? min(i0 + k, n - 1)
+                          : BUF ? (int64_t)gy_index32<BLK>(a, (uint32_t)min(i0 + k, n - 1), z)
+                                : gy_index<BLK>(a, min(i0 + k, n - 1));
         gv[k] = g.at_if(nd, j);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        far[k] = !interp_near(a, i0 + k, w[k], x[k], gv[k], o[k]);
+        far[k] = !interp_near<!PRE>(a, i0 + k, w[k], x[k], gv[k], o[k]);
     if (i0 + 4 <= n) {
         *reinterpret_cast<float4*>(a.out + i0) = make_float4(o[0], o[1], o[2], o[3]);
     } else {
@@ -1239,6 +1262,13 @@ __global__ __launch_bounds__(256) void k_interp_own(ZsArgs a)
         interp_own<BUF, true>(a);
     else
         interp_own<BUF, false>(a);
+}
+
+// The same phase from the x-pass words, alongside the y pass (Plan1::aux).
+template <bool BUF>
+__global__ __launch_bounds__(256) void k_interp_pre(ZsArgs a)
+{
+    interp_own<BUF, false, true>(a);
 }
 
 // Which waves of k_interp_own a block of k_interp_far takes.  Searches of
@@ -1354,12 +1384,39 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords, Fa
     }
 }
 
-template <bool BUF>
-static hipError_t launch_interp_search_t(const ZsArgs& a, int64_t blocks, hipStream_t s)
+// Geometry of the two phases: a thread of the streaming phase takes four
+// voxels; buffer loads by 32-bit byte offset while gy (natural or blocked)
+// stays below 2^31 bytes.
+static hipError_t interp_geom(const ZsArgs& a, bool force_wide, int64_t& blocks, bool& buf)
 {
-    const hipError_t e = launch_checked(k_interp_own<BUF>, dim3((unsigned)blocks), dim3(256), 0, s, a);
-    if (e != hipSuccess)
-        return e;
+    const int64_t n = a.nx * a.ny * a.nz;
+    if ((((uintptr_t)a.w1 | (uintptr_t)a.xq | (uintptr_t)a.out) & 15u) != 0)
+        return hipErrorInvalidValue; // the caller takes the unfused path instead
+    blocks = (n + 1023) / 1024;
+    if (blocks > 0x7FFFFFFF)
+        return hipErrorInvalidValue;
+    buf = word_capacity(a.nz, a.ny, a.nx) < ((int64_t)1 << 29) && !force_wide;
+    return hipSuccess;
+}
+
+// the streaming phase: from the y-pass words (k_interp_own) or, pre, from the
+// x-pass words (k_interp_pre)
+static hipError_t launch_interp_stream(const ZsArgs& a, bool force_wide, bool pre, hipStream_t s)
+{
+    int64_t blocks;
+    bool buf;
+    QAI_TRY(interp_geom(a, force_wide, blocks, buf));
+    const dim3 grid((unsigned)blocks), blk(256);
+    if (pre)
+        return buf ? launch_checked(k_interp_pre<true>, grid, blk, 0, s, a)
+                   : launch_checked(k_interp_pre<false>, grid, blk, 0, s, a);
+    return buf ? launch_checked(k_interp_own<true>, grid, blk, 0, s, a)
+               : launch_checked(k_interp_own<false>, grid, blk, 0, s, a);
+}
+
+template <bool BUF>
+static hipError_t launch_interp_far_t(const ZsArgs& a, int64_t blocks, hipStream_t s)
+{
     const int64_t nwords = blocks * 16; // flag_bytes(n) / 8
     const int64_t plane = a.nx * a.ny;
     FarMap fm{0, 0, 0, 0};
@@ -1374,17 +1431,13 @@ static hipError_t launch_interp_search_t(const ZsArgs& a, int64_t blocks, hipStr
     return launch_checked(k_interp_far<BUF>, dim3((unsigned)grid), dim3(256), 0, s, a, nwords, fm);
 }
 
-static hipError_t launch_interp_search(const ZsArgs& a, bool force_wide, hipStream_t s)
+// the search phase over the voxels the streaming phase flagged
+static hipError_t launch_interp_far(const ZsArgs& a, bool force_wide, hipStream_t s)
 {
-    const int64_t n = a.nx * a.ny * a.nz;
-    if ((((uintptr_t)a.w1 | (uintptr_t)a.xq | (uintptr_t)a.out) & 15u) != 0)
-        return hipErrorInvalidValue; // the caller takes the unfused path instead
-    const int64_t blocks = (n + 1023) / 1024;
-    if (blocks > 0x7FFFFFFF)
-        return hipErrorInvalidValue;
-    // buffer loads by 32-bit byte offset while gy (natural or blocked) stays below 2^31 bytes
-    const bool buf = word_capacity(a.nz, a.ny, a.nx) < ((int64_t)1 << 29) && !force_wide;
-    return buf ? launch_interp_search_t<true>(a, blocks, s) : launch_interp_search_t<false>(a, blocks, s);
+    int64_t blocks;
+    bool buf;
+    QAI_TRY(interp_geom(a, force_wide, blocks, buf));
+    return buf ? launch_interp_far_t<true>(a, blocks, s) : launch_interp_far_t<false>(a, blocks, s);
 }
 
 // --------------------------------------------------------- envelope pass
@@ -2974,6 +3027,11 @@ static hipError_t launch_lane2_t(EnvArgs a, int hb, hipStream_t s)
                        hb);
 }
 
+// Ring entries per lane: 32 where the pass has more than 2048 tiles (the
+// ring's LDS then limits a CU to 16 waves, the occupancy that pays at 512^3:
+// 664 us against 824 us with 64 entries and, with 16, an overflow in some
+// column), 64 below (no more waves to hold; fewer catch-ups and overflows:
+// 256^3 at rel. bound 5e-3, 222 -> 188 us).
 static hipError_t launch_lane2_y(EnvArgs a, int hb, const unsigned long long* b1count, uint32_t* ovf_flag,
                                  hipStream_t s)
 {
@@ -2981,8 +3039,10 @@ static hipError_t launch_lane2_y(EnvArgs a, int hb, const unsigned long long* b1
     const int64_t nxb = (a.nx + 63) >> 6;
     a.ntiles = (uint64_t)(nxb * a.nz);
     const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
-    return launch_checked(k_env_lane2_y<32, WPB>, dim3(grid_cap(groups, 1u << 20)), dim3(64 * WPB), 0, s, a, hb,
-                          b1count, ovf_flag);
+    const dim3 grid(grid_cap(groups, 1u << 20)), blk(64 * WPB);
+    if (a.ntiles <= 2048)
+        return launch_checked(k_env_lane2_y<64, WPB>, grid, blk, 0, s, a, hb, b1count, ovf_flag);
+    return launch_checked(k_env_lane2_y<32, WPB>, grid, blk, 0, s, a, hb, b1count, ovf_flag);
 }
 
 template <int AXIS>
@@ -3286,13 +3346,6 @@ void final_buffers(int64_t nz, int64_t ny, int64_t nx, int& w1, int& w2)
     w2 = c2;
 }
 
-#define QAI_TRY(expr)                   \
-    do {                                \
-        hipError_t e_ = (expr);         \
-        if (e_ != hipSuccess)           \
-            return e_;                  \
-    } while (0)
-
 // Automatic pass algorithm.  The streaming kernels give one wavefront to 64
 // columns and walk the whole column, so they need many column tiles to fill
 // the GPU; the windowed search is parallel over every voxel but costs the
@@ -3482,6 +3535,21 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
     const bool any_tap = tp.q || tp.b1 || tp.sb || tp.s || tp.d1sq || tp.b2 || tp.d2sq || tp.w;
     const bool aligned = (((uintptr_t)buf[w1] | (uintptr_t)p.xq | (uintptr_t)p.out) & 15u) == 0;
     const bool search = p.nz > 1 && !any_tap && t_in.env_algo[2] < 0 && p.flags && aligned;
+    // the streaming phase of step E needs only the x-pass words: with a side
+    // stream it runs there while the y pass (issue-bound, LDS-limited to a
+    // few waves per SIMD) runs here; the search phase joins after both
+    const bool overlap = search && p.ny > 1 && p.aux;
+    if (overlap) {
+        const int w2b = o0; // the search phase's distance words: the x-pass buffer (see nx2 below)
+        ZsArgs zp = {buf[w1], nullptr, buf[w2b], p.xq, p.out, p.flags, p.nx, p.ny, p.nz, p.eta * p.eb, p.power, false,
+                     nullptr, nullptr, buf[c2]};
+        QAI_TRY(hipEventRecord(p.aux->fork, s));
+        QAI_TRY(hipStreamWaitEvent(p.aux->s, p.aux->fork, 0));
+        prof_begin("edt2_z_stream", p.aux->s);
+        QAI_TRY(launch_interp_stream(zp, t.force_wide != 0, true, p.aux->s));
+        prof_end(p.aux->s);
+        QAI_TRY(hipEventRecord(p.aux->join, p.aux->s));
+    }
     bool blk = false;
     const unsigned long long* b1est = nullptr;
     uint32_t* ovf = nullptr;
@@ -3514,10 +3582,20 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
         // last pass of step D only at needed voxels, fused with step E
         const int nx2 = (c2 == o0) ? o1 : o0;
         ZsArgs za = {buf[w1], buf[c2], buf[nx2], p.xq, p.out, p.flags, p.nx, p.ny, p.nz, p.eta * p.eb, p.power, blk,
-                     b1est, ovf};
-        prof_begin("edt2_z_interp", s);
-        QAI_TRY(launch_interp_search(za, t.force_wide != 0, s));
-        prof_end(s);
+                     b1est, ovf, nullptr};
+        if (overlap) {
+            if (nx2 != o0)
+                return hipErrorInvalidValue; // the streaming phase relied on w2 being the x-pass buffer
+            QAI_TRY(hipStreamWaitEvent(s, p.aux->join, 0));
+            prof_begin("edt2_z_search", s);
+            QAI_TRY(launch_interp_far(za, t.force_wide != 0, s));
+            prof_end(s);
+        } else {
+            prof_begin("edt2_z_interp", s);
+            QAI_TRY(launch_interp_stream(za, t.force_wide != 0, false, s));
+            QAI_TRY(launch_interp_far(za, t.force_wide != 0, s));
+            prof_end(s);
+        }
         p.w1_final = buf[w1];
         p.w2_final = buf[nx2];
         return hipSuccess;
@@ -3539,6 +3617,37 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
     prof_end(s);
     p.w1_final = buf[w1];
     p.w2_final = buf[c2];
+    return hipSuccess;
+}
+
+static std::mutex g_aux_mu;
+static Aux g_aux[64];
+
+hipError_t aux_for(int dev, Aux*& out)
+{
+    if (dev < 0 || dev >= 64)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    Aux& x = g_aux[dev];
+    if (!x.s) {
+        hipStream_t st = nullptr;
+        hipEvent_t f = nullptr, j = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&f, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (j) (void)hipEventDestroy(j);
+            if (f) (void)hipEventDestroy(f);
+            if (st) (void)hipStreamDestroy(st);
+            return e;
+        }
+        x.fork = f;
+        x.join = j;
+        x.s = st;
+    }
+    out = &x;
     return hipSuccess;
 }
 

@@ -277,6 +277,9 @@ int qai_autotune(const float* field, const int64_t dims[3], float eb, void* ws, 
     pl.eta = 0.9f;
     pl.power = 1.0f;
     ws_buffers(ws, pl);
+    if ((e = qai::aux_for(dev, pl.aux)) != hipSuccess)
+        return fail_hip(e, "side stream");
+    std::lock_guard<std::mutex> lk(pl.aux->mu);
     qai::Tuning base;
     qai::default_tuning(base);
     qai::Tuning pick;

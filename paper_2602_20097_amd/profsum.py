@@ -27,7 +27,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 STAGES = [
     (r"k_seed_(lane|seg|slab|xscan|lines)<0", "seed1_xscan"),
     (r"k_seed_(lane|seg|slab|xscan|lines)<1", "seed2_xscan"),
-    (r"k_interp_(own|far)", "edt2_z_interp"),
+    (r"k_interp_own", "edt2_z_interp"),
+    (r"k_interp_pre", "edt2_z_stream"),
+    (r"k_interp_far", "edt2_z_search"),
     (r"k_edt1_yz", "edt1_yz"),
     (r"k_env_lane2_y\b", "edt2_y"),
     (r"k_interp\b", "interp"),

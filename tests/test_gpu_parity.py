@@ -333,16 +333,17 @@ def test_tall_columns_with_few_tiles(shape, rel):
 
 
 def test_envelope_ring_overflow_hands_the_y_pass_to_the_banded_pass():
-    """Sparse B2 over long x-lines: some column's live window outgrows the
+    """Sparse B2 over long x-lines in a field of more than 2048 column tiles
+    (32 ring entries per lane): some column's live window outgrows the
     per-lane envelope's ring in the second EDT's y pass, the pass raises the
     header word and the banded pass (gated on it) redoes the whole y pass in
     the natural layout, which the needed-voxel search then reads.  The output
     matches the tapped call and the oracle."""
     import paper_2602_20097_amd as qai
-    x32, xq, q, eb = synth.quantize(synth.grf((16, 128, 1024), 3.7, 77), 1.6e-4)
+    x32, xq, q, eb = synth.quantize(synth.grf((130, 128, 1024), 3.7, 77), 1.6e-4)
     t = torch.from_numpy(xq).cuda()
     ws = qai.new_workspace(t.shape)
     qai.mitigate(t, eb, workspace=ws)
     torch.cuda.synchronize()
     assert int(ws[68:72].view(torch.int32).item()) != 0  # header word 17: the ring overflowed
-    assert_parity(xq, eb, label="ring overflow (16, 128, 1024)")
+    assert_parity(xq, eb, label="ring overflow (130, 128, 1024)")
