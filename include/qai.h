@@ -20,6 +20,13 @@
  *
  * Determinism: results are bit-identical across runs, launch shapes and
  * autotuner choices.  Calls are reentrant when their workspaces differ.
+ *
+ * Streams: a call's work is ordered after what stream holds before it and
+ * before what is enqueued on stream after it.  On a 3-D field without taps
+ * part of step E runs on a side stream the library keeps per device (created
+ * on the device's first call, kept until the process ends), joined to stream
+ * with events.  While stream is being captured into a graph, and in
+ * qai_mitigate_noalloc, every launch stays on stream.
  */
 #ifndef QAI_H
 #define QAI_H

@@ -261,8 +261,8 @@ constexpr size_t kPartialOffset = 256; // FP64 partial sums of the adjoint reduc
 
 
 // side: run the streaming part of step E on the device's side stream
-// alongside the second EDT's y pass (qai::Aux); the allocation-free entry
-// point keeps every launch on the caller's stream
+// alongside the second EDT's y pass (qai::Aux), unless stream is being
+// captured; the allocation-free entry point keeps every launch on stream
 int plain_checked(const float* field, const int64_t dims[3], float eb, const qai_params* params, void* ws,
                   size_t ws_bytes, float* out, const qai_taps* taps, void* stream, bool side)
 {
@@ -304,7 +304,7 @@ int plain_checked(const float* field, const int64_t dims[3], float eb, const qai
         pl.taps = *taps;
     const qai::Tuning t = tuning_for(dims);
     std::unique_lock<std::mutex> lk;
-    if (side) {
+    if (side && !qai::stream_capturing((hipStream_t)stream)) {
         if ((e = qai::aux_for(dev, pl.aux)) != hipSuccess)
             return fail_hip(e, "side stream");
         lk = std::unique_lock<std::mutex>(pl.aux->mu);

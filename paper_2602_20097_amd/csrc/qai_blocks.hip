@@ -41,6 +41,7 @@ constexpr int kSides = 4;
 struct Sides {
     hipStream_t side[kSides] = {};
     hipEvent_t fork = nullptr, join[kSides] = {};
+    Aux* aux[kSides] = {};    // per side stream: the side stream of its blocks' step E
 };
 std::mutex g_sides_mu;
 std::map<int, Sides> g_sides;
@@ -58,6 +59,15 @@ hipError_t sides_for(int dev, Sides*& out)
         e = hipStreamCreateWithFlags(&sd.side[k], hipStreamNonBlocking);
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&sd.join[k], hipEventDisableTiming);
+        if (e == hipSuccess) {
+            Aux* x = new Aux();
+            sd.aux[k] = x;
+            e = hipStreamCreateWithFlags(&x->s, hipStreamNonBlocking);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&x->fork, hipEventDisableTiming);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&x->join, hipEventDisableTiming);
+        }
     }
     if (e != hipSuccess)
         return e; // (what was created stays: a failed call is not retried here)
@@ -283,6 +293,9 @@ int qai_mitigate_blocks(const float* field, const int64_t dims[3], float eb, con
     QAI_BTRY(qai::sides_for(dev, sd));
     for (Blk& b : bl)
         QAI_BTRY(qai::copy_region(field, dims, b.reg, b.real, (void*)b.plan.xq, false, s));
+    if (!qai::stream_capturing(s))
+        for (size_t i = 0; i < bl.size(); ++i)
+            bl[i].plan.aux = sd->aux[i % qai::kSides]; // guarded by g_sides_mu
     QAI_BTRY(qai::fork_sides(*sd, s));
     if (!approx) {
         for (size_t i = 0; i < bl.size(); ++i)

@@ -136,9 +136,12 @@ int qai_mitigate_coded(const qai_coded* code, const int64_t dims[3], float eb, c
     pl.eta = p.eta;
     pl.power = p.power;
     ws_buffers(ws, pl);
-    if ((e = qai::aux_for(dev, pl.aux)) != hipSuccess)
-        return fail_hip(e, "side stream");
-    std::lock_guard<std::mutex> lk(pl.aux->mu);
+    std::unique_lock<std::mutex> lk;
+    if (!qai::stream_capturing((hipStream_t)stream)) {
+        if ((e = qai::aux_for(dev, pl.aux)) != hipSuccess)
+            return fail_hip(e, "side stream");
+        lk = std::unique_lock<std::mutex>(pl.aux->mu);
+    }
     e = qai::run_plain(pl, tuning_for(dims), (hipStream_t)stream);
     return e == hipSuccess ? QAI_OK : fail_hip(e, "kernel launch");
 }

@@ -167,6 +167,9 @@ struct Aux {
     hipEvent_t fork = nullptr, join = nullptr;
 };
 hipError_t aux_for(int dev, Aux*& out);
+// True while s is being captured into a graph (or its state is unknown): the
+// side stream is then left out, every launch stays on s.
+bool stream_capturing(hipStream_t s);
 
 struct Plan1 {
     const Coded* coded;   // when set, the indices come from this code and x' is written to out

@@ -2446,7 +2446,7 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
             sl[row & 3] = v;
             if ((row & 3) == 3 || row == n - 1) {
                 const u32x4 q = *reinterpret_cast<const u32x4*>(sl);
-                __builtin_amdgcn_raw_buffer_store_b128(q, rout, bo + (uint32_t)(row >> 2) * bstep, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b128(q, rout, bo + __umul24((uint32_t)(row >> 2), bstep), 0, 0);
             }
         };
 
@@ -2461,8 +2461,11 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
         bool ovf = false;
 
         // the owner of row e: step while the next entry is strictly better
+        // (24-bit products: lane2_geometry keeps lines below 1024 rows, so
+        // 2 e dfh and e (e - 2 fh0) fit; a 32-bit multiply costs four times as much)
         auto walk = [&]() {
-            if (lo < top && dfc < 2 * e * dfh) {
+            const int e2 = 2 * e;
+            if (lo < top && dfc < __mul24(e2, dfh)) {
 #pragma unroll 1
                 do {
                     ++lo;
@@ -2471,57 +2474,53 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
                     dfc = (int)(f2p >> hb) - fc0;
                     dfh = (int)(f2p & hm) - fh0;
                     f2p = rl[SLOT(lo + 2)];
-                } while (lo < top && dfc < 2 * e * dfh);
+                } while (lo < top && dfc < __mul24(e2, dfh));
             }
-            be = (uint32_t)(fc0 + e * (e - 2 * fh0));
+            be = (uint32_t)(fc0 + __mul24(e, e - 2 * fh0));
         };
 
+        // A lane whose live window fills the ring sets ovf and holds be at
+        // "none" from then on: its column is redone (the banded pass or the
+        // outward search below), so its ring may be overwritten.  "Row e is
+        // final" then reads be <= (i + 1 - e)^2 alone: a finite be means a
+        // site was read (top >= lo), and e = i + 1 never passes (its owner
+        // lies at least a row away).
         auto row_step = [&](int i, uint32_t w) {
             if (w != QAI_WORD_INF && !ovf) {
                 const int g = (int)(w >> 2);
                 const int cw = g + i * i;
-                if (top > lo) {
-                    bool rm = __mul24(dc, i - h0) - __mul24(cw - c0, dh) > 0;
+                bool rm = top > lo && __mul24(dc, i - h0) - __mul24(cw - c0, dh) > 0;
 #pragma unroll 1
-                    while (rm) {
-                        --top;
-                        c0 -= dc;
-                        h0 -= dh;
-                        dc = c0 - (int)(t2p >> hb);
-                        dh = h0 - (int)(t2p & hm);
-                        t2p = rl[SLOT(top - 2)];
-                        rm = top > lo && __mul24(dc, i - h0) - __mul24(cw - c0, dh) > 0;
-                    }
+                while (rm) {
+                    --top;
+                    c0 -= dc;
+                    h0 -= dh;
+                    dc = c0 - (int)(t2p >> hb);
+                    dh = h0 - (int)(t2p & hm);
+                    t2p = rl[SLOT(top - 2)];
+                    rm = top > lo && __mul24(dc, i - h0) - __mul24(cw - c0, dh) > 0;
                 }
-                if (top - lo + 1 >= C) {
-                    ovf = true;
-                } else {
-                    t2p = rl[SLOT(top - 1)];
-                    ++top;
-                    const uint32_t pk = ((uint32_t)cw << hb) | (uint32_t)i;
-                    rl[SLOT(top)] = pk;
-                    dc = cw - c0;
-                    dh = i - h0;
-                    c0 = cw;
-                    h0 = i;
-                    be = min(be, (uint32_t)(g + __mul24(e - i, e - i)));
-                    const int ws = top - lo;
-                    if (ws == 0) {
-                        fc0 = cw;
-                        fh0 = i;
-                    }
-                    if (ws == 1) {
-                        dfc = dc;
-                        dfh = dh;
-                    }
-                    if (ws == 2)
-                        f2p = pk;
-                }
+                ovf = top - lo + 1 >= C;
+                t2p = rl[SLOT(top - 1)];
+                ++top;
+                const uint32_t pk = ((uint32_t)cw << hb) | (uint32_t)i;
+                rl[SLOT(top)] = pk;
+                dc = cw - c0;
+                dh = i - h0;
+                c0 = cw;
+                h0 = i;
+                be = ovf ? 0xFFFFFFFFu : min(be, (uint32_t)(g + __mul24(e - i, e - i)));
+                const int ws = top - lo;
+                fc0 = ws == 0 ? cw : fc0;
+                fh0 = ws == 0 ? i : fh0;
+                dfc = ws == 1 ? dc : dfc;
+                dfh = ws == 1 ? dh : dfh;
+                f2p = ws == 2 ? pk : f2p;
             }
             // one emission slot per row (unblocked: a lane with nothing final
             // repeats its last store, so the memory operations per row stay fixed)
             const int q = i + 1 - e;
-            const bool fin = !ovf && e <= i && top >= lo && be <= (uint32_t)__mul24(q, q);
+            const bool fin = be <= (uint32_t)__mul24(q, q);
             if (BLK) {
                 if (fin)
                     emit_blk(e, be << 2);
@@ -2544,7 +2543,7 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
 #pragma unroll 1
             for (int it = 0; it < n; ++it) {
                 const int q = i + 1 - e;
-                const bool fin = !ovf && top - lo + 1 > C - 9 && e <= i && be <= (uint32_t)__mul24(q, q);
+                const bool fin = top - lo + 1 > C - 9 && be <= (uint32_t)__mul24(q, q);
                 if (__ballot(fin) == 0ull)
                     break;
                 if (fin) {
@@ -3625,6 +3624,7 @@ static Aux g_aux[64];
 
 hipError_t aux_for(int dev, Aux*& out)
 {
+    out = nullptr;
     if (dev < 0 || dev >= 64)
         return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> lk(g_aux_mu);
@@ -3649,6 +3649,12 @@ hipError_t aux_for(int dev, Aux*& out)
     }
     out = &x;
     return hipSuccess;
+}
+
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone;
 }
 
 hipError_t run_plain(Plan1& p, const Tuning& t, hipStream_t s)
