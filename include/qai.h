@@ -115,8 +115,10 @@ size_t qai_workspace_bytes(const int64_t dims[3]);
  * every voxel whose weight depends on it (S != 0 and not on B1), which is all
  * qai_backward reads; keep the workspace untouched until then.  On a 3-D field
  * without taps, with default pass choices and 16-byte aligned field and out,
- * the second EDT's last pass runs only at those voxels, so its words elsewhere
- * are left unspecified; every other call writes them at every voxel. */
+ * and on a 2-D field without taps whose y pass of the second EDT is on
+ * automatic or the direct search (edt2_algo[0] -1 or 5), the second EDT's last
+ * pass runs only at those voxels, so its words elsewhere are left unspecified;
+ * every other call writes them at every voxel. */
 int qai_mitigate_ex(const float* field, const int64_t dims[3], float eb, const qai_params* params,
                     void* ws, size_t ws_bytes, float* out, const qai_taps* taps, void* stream);
 
@@ -222,17 +224,20 @@ typedef struct qai_tuning {
                               4 streaming outward search (short distances), 5 outward search
                               per voxel from the pass input (short distances, any number
                               of column tiles); -1 (the default)
-                              picks per pass: 1 when the pass has fewer than 4096 tiles of
-                              64 columns, else 4; on a 3-D field with both passes at -1 they
+                              picks per pass: 5 for the y pass of a 2-D field, else 1 when
+                              the pass has fewer than 4096 tiles of 64 columns, else 4; on a
+                              3-D field with both passes at -1 they
                               run as one search over (y, z) offsets, with the separable passes
                               (chosen as for -1) behind it where that search does not apply */
     int32_t edt2_algo[2];  /* the same for the second EDT, plus 3: per-lane online envelope
                               (payload-free words; falls back to 0 where its packed ring
-                              entries would not fit 32 bits); -1 (the default) picks 1 below
-                              256 tiles, else 3.  For the z pass of a 3-D call without taps
+                              entries would not fit 32 bits); -1 (the default) picks 5 for
+                              the y pass of a 2-D field, else 1 below 256 tiles, else 3.  For the z pass of a 3-D call without taps
                               (16-byte aligned field and out), -1 computes the distance to B2
                               only where step E needs it, by an exact outward search along z
-                              fused with step E; an explicit choice runs the whole pass */
+                              fused with step E; an explicit choice runs the whole pass.
+                              The y pass of a 2-D call without taps at -1 or 5 runs the
+                              direct search only where step E needs it, fused with step E */
     int32_t edt1_ring;     /* live-window ring entries of the streaming envelope: 16, 32 or 64 */
     int32_t edt2_ring;
     int32_t tile_log2[2];  /* log2 of x-columns per tile of the tiled variants, y and z (-1: auto) */

@@ -30,6 +30,7 @@ STAGES = [
     (r"k_interp_own", "edt2_z_interp"),
     (r"k_interp_pre", "edt2_z_stream"),
     (r"k_interp_far", "edt2_z_search"),
+    (r"k_interp_dir", "edt2_y_interp"),
     (r"k_edt1_yz", "edt1_yz"),
     (r"k_env_lane2_y\b", "edt2_y"),
     (r"k_interp\b", "interp"),

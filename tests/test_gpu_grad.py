@@ -33,7 +33,19 @@ def gpu_backward(xq, eb, g, eta, power):
 
 @pytest.mark.parametrize("eta,power", [(0.9, 1.0), (0.6, 2.0), (1.1, 0.5)])
 def test_adjoint_matches_fp64_autograd(eta, power):
-    x32, xq, eb = field()
+    adjoint_case(field(), eta, power)
+
+
+@pytest.mark.parametrize("shape", [(1, 96, 130), (1, 257, 300)])
+def test_adjoint_of_a_2d_field_matches_fp64_autograd(shape):
+    """2-D fields without taps take the second EDT's y pass only where step
+    E needs it (fused with step E): the distance words the adjoint reads are
+    written there."""
+    adjoint_case(field(shape=shape, seed=sum(shape)), 0.9, 1.0)
+
+
+def adjoint_case(fld, eta, power):
+    x32, xq, eb = fld
     r = oracle.qai(xq, eb, eta, power)
     g = np.random.default_rng(7).standard_normal(xq.shape).astype(np.float32)
     e = torch.tensor(float(np.float32(eta)), dtype=torch.float64, requires_grad=True)
