@@ -2529,10 +2529,12 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
 
         // the owner of row e: step while the next entry is strictly better
         // (24-bit products: lane2_geometry keeps lines below 1024 rows, so
-        // 2 e dfh and e (e - 2 fh0) fit; a 32-bit multiply costs four times as much)
+        // 2 e dfh and e (e - 2 fh0) fit; a 32-bit multiply costs four times as
+        // much.  2 e and dfh are never negative: the unsigned form needs no
+        // sign extension of its operands)
         auto walk = [&]() {
             const int e2 = 2 * e;
-            if (lo < top && dfc < __mul24(e2, dfh)) {
+            if (lo < top && dfc < (int)__umul24((uint32_t)e2, (uint32_t)dfh)) {
 #pragma unroll 1
                 do {
                     ++lo;
@@ -2541,7 +2543,7 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
                     dfc = (int)(f2p >> hb) - fc0;
                     dfh = (int)(f2p & hm) - fh0;
                     f2p = rl[SLOT(lo + 2)];
-                } while (lo < top && dfc < __mul24(e2, dfh));
+                } while (lo < top && dfc < (int)__umul24((uint32_t)e2, (uint32_t)dfh));
             }
             be = (uint32_t)(fc0 + __mul24(e, e - 2 * fh0));
         };
@@ -2553,7 +2555,7 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
         // site was read (top >= lo), and e = i + 1 never passes (its owner
         // lies at least a row away).
         auto row_step = [&](int i, uint32_t w) {
-            if (w != QAI_WORD_INF && !ovf) {
+            if ((w != QAI_WORD_INF) & !ovf) { // one branch for both conditions
                 const int g = (int)(w >> 2);
                 const int cw = g + i * i;
                 bool rm = top > lo && __mul24(dc, i - h0) - __mul24(cw - c0, dh) > 0;
@@ -2586,8 +2588,8 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
             }
             // one emission slot per row (unblocked: a lane with nothing final
             // repeats its last store, so the memory operations per row stay fixed)
-            const int q = i + 1 - e;
-            const bool fin = be <= (uint32_t)__mul24(q, q);
+            const int q = i + 1 - e; // 0 <= q <= i + 1
+            const bool fin = be <= __umul24((uint32_t)q, (uint32_t)q);
             if (BLK) {
                 if (fin)
                     emit_blk(e, be << 2);
@@ -2610,7 +2612,7 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
 #pragma unroll 1
             for (int it = 0; it < n; ++it) {
                 const int q = i + 1 - e;
-                const bool fin = top - lo + 1 > C - 9 && be <= (uint32_t)__mul24(q, q);
+                const bool fin = top - lo + 1 > C - 9 && be <= __umul24((uint32_t)q, (uint32_t)q);
                 if (__ballot(fin) == 0ull)
                     break;
                 if (fin) {
