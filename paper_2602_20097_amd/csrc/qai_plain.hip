@@ -1045,8 +1045,8 @@ struct ZsArgs {
 // stores pay.  Elsewhere many voxels are needed (up to two thirds of a
 // field at rel. bound 1e-2) and the search's reads of natural rows touch a
 // quarter of the cache lines, so the natural layout goes.  The y pass and
-// the search read the same estimate and so agree on the layout.  The same
-// test stands the fused first-EDT search down (k_edt1_yz).
+// the search read the same estimate and so agree on the layout.  The fused
+// first-EDT search (k_edt1_yz) stands down below 80% on the same estimate.
 __device__ __forceinline__ bool blocked_layout(const unsigned long long* b1count, uint64_t n)
 {
     return *b1count * 10ull >= n * 9ull;
@@ -3200,10 +3200,10 @@ __global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide, cons
     const IDX nq = plane * nz / 4;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ntab = c_yz.n;
-    // With B1 below 90% of the field the searches would be long and often end
+    // With B1 below 80% of the field the searches would be long and often end
     // beyond the disc: the pass stands down before it reads anything (block 0
     // raises the gate of the separable passes)
-    if (*b1count * 10ull < (unsigned long long)(plane * nz) * 9ull) {
+    if (*b1count * 5ull < (unsigned long long)(plane * nz) * 4ull) {
         if (blockIdx.x == 0 && tid == 0)
             atomicOr(wide, 1u);
         return;

@@ -211,7 +211,7 @@ def test_handoff_layout_follows_the_b1_density(rel, dense):
 
 def test_first_edt_beyond_the_search_disc():
     """The first EDT's y and z passes run as one search over a disc of radius
-    12 around each voxel when B1 covers at least 90% of the field; a voxel
+    12 around each voxel when B1 covers at least 80% of the field; a voxel
     farther from B1 raises a flag and the separable passes behind the search
     recompute the field, and with sparser B1 the search stands down for
     them.  Dense B1 (random indices) around a 28-voxel plateau puts the
