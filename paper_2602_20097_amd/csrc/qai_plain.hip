@@ -699,6 +699,29 @@ __global__ __launch_bounds__(64 * WPB) void k_seed_lane(SlabArgs A)
         // "no site", which occurs only when B1 is empty, everywhere at once)
         // plus 4 on B1 (distance 0).
         auto keys = [&](const uint32_t (&r)[V], bool ok, uint32_t (&k)[V]) {
+            if constexpr (SA && !CODED) {
+                // recover_q's fast case (the product with the rounded
+                // reciprocal within 0.4 of an integer below 2^18) tested for
+                // the lane's V voxels together; only a wave where some voxel
+                // fails it takes recover_q voxel by voxel
+                float t[V], rt[V];
+                float dev = 0.0f, mag = 0.0f;
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const bool in = ok && x0 + j < nx;
+                    t[j] = (in ? __uint_as_float(r[j]) : 0.0f) * a.inv2eb;
+                    rt[j] = rintf(t[j]);
+                    dev = fmaxf(dev, fabsf(t[j] - rt[j]));
+                    mag = fmaxf(mag, fabsf(t[j]));
+                }
+                // (a NaN compares false: such a lane takes the voxel-wise path)
+                if (__ballot(!(mag < 262144.0f && dev <= 0.4f)) == 0ull) {
+#pragma unroll
+                    for (int j = 0; j < V; ++j)
+                        k[j] = (uint32_t)(int32_t)rt[j] ^ 0x80000000u;
+                    return;
+                }
+            }
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 const bool in = ok && x0 + j < nx;

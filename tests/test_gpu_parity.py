@@ -84,6 +84,20 @@ def test_adversarial_fields():
     assert_parity(q.astype(np.float32), 0.5, label="long-y")
 
 
+def test_indices_of_values_off_the_quantization_grid():
+    """x' that are not decompressed values: for about a fifth of the voxels the
+    product with the rounded reciprocal of 2 eb lies farther than 0.4 from an
+    integer, and some indices lie above 2^18, so the seed pass takes the exact
+    quotient there (a wave at a time, voxel by voxel).  q and every other tap
+    match the oracle."""
+    rng = np.random.default_rng(5)
+    xq = (rng.standard_normal((9, 40, 70)) * 3.7).astype(np.float32)
+    xq[4, 20, 10:30] = np.linspace(0.2 * 2.7e5, 0.2 * 4.1e5, 20).astype(np.float32)
+    frac = np.abs(xq / np.float32(0.2) - np.rint(xq / np.float32(0.2)))
+    assert (frac > 0.4).mean() > 0.1
+    assert_parity(xq, 0.1, label="off-grid values")
+
+
 def test_parameters_eta_power():
     x32, xq, q, eb = synth.make_workload("grf64_k3_eb1e-2")
     for eta, p in ((0.5, 1.0), (1.0, 2.0), (0.9, 0.5)):
