@@ -2866,11 +2866,18 @@ static hipError_t launch_seed_lane(const SeedArgs& in, int tz, hipStream_t s)
     case 3: return launch_seed_lane_t<MODE, 3>(in, tz, s);
     case 4: return launch_seed_lane_t<MODE, 4>(in, tz, s);
     case 5: return launch_seed_lane_t<MODE, 5>(in, tz, s);
-    case 6: return launch_seed_lane_t<MODE, 6>(in, tz, s);
+    case 6:
+        // step A in workgroups of four waves (384^3: 151 -> 127 us; step C keeps eight)
+        if constexpr (MODE == 0)
+            return launch_seed_lane_t<MODE, 6, 1, 4>(in, tz, s);
+        else
+            return launch_seed_lane_t<MODE, 6>(in, tz, s);
     case 7: return launch_seed_lane_t<MODE, 7>(in, tz, s);
     default:
         // step A on 449..512-voxel lines in workgroups of four waves (512^3:
-        // 290 -> 250 us against eight; step C keeps eight: 216 against 229 us)
+        // 290 -> 250 us against eight, 100x500x500 104 -> 81 us; step C keeps
+        // eight: 216 against 229 us on 512^3): the barrier of every plane
+        // waits for fewer waves, the halo rows cost more
         if constexpr (MODE == 0)
             return launch_seed_lane_t<MODE, 8, 1, 4>(in, tz, s);
         else
@@ -2926,7 +2933,7 @@ hipError_t launch_seed_coded(const SeedArgs& in, int tz, hipStream_t s)
     case 1: return launch_seed_coded_t<1>(in, tz, s);
     case 2: return launch_seed_coded_t<2>(in, tz, s);
     case 4: return launch_seed_coded_t<4>(in, tz, s);
-    case 8: return launch_seed_coded_t<8>(in, tz, s);
+    case 8: return launch_seed_coded_t<8, 1, 4>(in, tz, s); // four waves, as the plain step A
     default: return hipErrorInvalidValue;
     }
 }
