@@ -2858,30 +2858,23 @@ static hipError_t launch_seed_lane(const SeedArgs& in, int tz, hipStream_t s)
         return launch_seed_lane_t<MODE, 8, 8, 16>(in, tz, s);
     if (in.nx > 1024)
         return launch_seed_lane_t<MODE, 8, 4>(in, tz, s);
+    // step A in workgroups of four waves from four voxels per lane up: each
+    // plane's barrier waits for fewer waves (seed1 on 512^3 290 -> 250 us,
+    // 100x500x500 104 -> 81, 384^3 151 -> 127, 96x256x768 77 -> 66,
+    // 200x300x300 80 -> 74 us; level on 128x128x1024 and 300x400x400).  Step C
+    // keeps eight (512^3: 216 against 229 us; 384^3 118 against 129 us).
+    constexpr int W4 = MODE == 0 ? 4 : 8;
     if (in.nx > 512)
-        return launch_seed_lane_t<MODE, 8, 2>(in, tz, s);
+        return launch_seed_lane_t<MODE, 8, 2, W4>(in, tz, s);
     switch ((int)((in.nx + 63) / 64)) {
     case 1: return launch_seed_lane_t<MODE, 1>(in, tz, s);
     case 2: return launch_seed_lane_t<MODE, 2>(in, tz, s);
     case 3: return launch_seed_lane_t<MODE, 3>(in, tz, s);
-    case 4: return launch_seed_lane_t<MODE, 4>(in, tz, s);
-    case 5: return launch_seed_lane_t<MODE, 5>(in, tz, s);
-    case 6:
-        // step A in workgroups of four waves (384^3: 151 -> 127 us; step C keeps eight)
-        if constexpr (MODE == 0)
-            return launch_seed_lane_t<MODE, 6, 1, 4>(in, tz, s);
-        else
-            return launch_seed_lane_t<MODE, 6>(in, tz, s);
-    case 7: return launch_seed_lane_t<MODE, 7>(in, tz, s);
-    default:
-        // step A on 449..512-voxel lines in workgroups of four waves (512^3:
-        // 290 -> 250 us against eight, 100x500x500 104 -> 81 us; step C keeps
-        // eight: 216 against 229 us on 512^3): the barrier of every plane
-        // waits for fewer waves, the halo rows cost more
-        if constexpr (MODE == 0)
-            return launch_seed_lane_t<MODE, 8, 1, 4>(in, tz, s);
-        else
-            return launch_seed_lane_t<MODE, 8>(in, tz, s);
+    case 4: return launch_seed_lane_t<MODE, 4, 1, W4>(in, tz, s);
+    case 5: return launch_seed_lane_t<MODE, 5, 1, W4>(in, tz, s);
+    case 6: return launch_seed_lane_t<MODE, 6, 1, W4>(in, tz, s);
+    case 7: return launch_seed_lane_t<MODE, 7, 1, W4>(in, tz, s);
+    default: return launch_seed_lane_t<MODE, 8, 1, W4>(in, tz, s);
     }
 }
 
