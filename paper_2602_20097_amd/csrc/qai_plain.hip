@@ -3210,8 +3210,9 @@ constexpr YzTable make_yz_table()
 __constant__ YzTable c_yz = make_yz_table();
 
 // Four consecutive voxels of a row per quad (nx a multiple of 4).  A block
-// takes 1024 quads at a time, four per thread 256 apart (their loads in
-// flight together), writes the quads whose four voxels are sites (distance
+// takes 512 quads at a time, two per thread 256 apart, their loads in flight
+// together (against four per thread: 256x384x384 65 -> 58 us, 512^3 level;
+// eight took 512^3 from 330 to 430 us), writes the quads whose four voxels are sites (distance
 // 0: final, most of the field) and lists the others in LDS; its threads then
 // search the listed quads one each, so only as many waves as the list needs
 // run the search.  Each offset of the disc is one 16-byte load serving a
@@ -3221,7 +3222,7 @@ __constant__ YzTable c_yz = make_yz_table();
 template <typename IDX>
 __global__ __launch_bounds__(256) void k_edt1_yz(EnvArgs a, uint32_t* wide, const unsigned long long* b1count)
 {
-    constexpr int U = 4;
+    constexpr int U = 2;
     __shared__ uint16_t list[256 * U];
     __shared__ int wsum[4 * U];
     __shared__ uint32_t stop;
@@ -3357,7 +3358,7 @@ static hipError_t launch_edt1_yz(const EnvArgs& a, uint32_t* wide, const unsigne
                                  bool force_wide, hipStream_t s)
 {
     const int64_t n = a.nx * a.ny * a.nz, nq = n / 4;
-    const uint32_t grid = grid_cap((uint64_t)((nq + 1023) / 1024), 1u << 20);
+    const uint32_t grid = grid_cap((uint64_t)((nq + 511) / 512), 1u << 20); // 512 quads per block
     if (n < ((int64_t)1 << 32) && !force_wide)
         return launch_checked(k_edt1_yz<uint32_t>, dim3(grid), dim3(256), 0, s, a, wide, b1count);
     return launch_checked(k_edt1_yz<int64_t>, dim3(grid), dim3(256), 0, s, a, wide, b1count);
