@@ -2748,16 +2748,18 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2(EnvArgs a, int hb)
     env_lane2<AXIS, C, WPB, BLK>(a, hb, ring, stage);
 }
 
-// The y pass ahead of the needed-voxel search: its output layout chosen on
-// the device (blocked_layout) from the first seed pass's B1 estimate, blocked
-// where there is none (b1count null).
+// The second EDT's y pass by the per-lane envelope.  Ahead of the
+// needed-voxel search its output layout is chosen on the device
+// (blocked_layout) from the first seed pass's B1 estimate, blocked where
+// there is none (b1count null); ahead of a whole z pass (natural) it is the
+// natural layout.
 template <int C, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_env_lane2_y(EnvArgs a, int hb, const unsigned long long* b1count,
-                                                          uint32_t* ovf_flag)
+                                                          uint32_t* ovf_flag, bool natural)
 {
     __shared__ uint32_t ring[WPB * C * 64];
     __shared__ __align__(16) uint32_t stage[WPB * 64 * 4];
-    if (!b1count || blocked_layout(b1count, (uint64_t)(a.nx * a.ny * a.nz)))
+    if (!natural && (!b1count || blocked_layout(b1count, (uint64_t)(a.nx * a.ny * a.nz))))
         env_lane2<1, C, WPB, true>(a, hb, ring, stage, ovf_flag);
     else
         env_lane2<1, C, WPB, false>(a, hb, ring, stage, ovf_flag);
@@ -3130,7 +3132,7 @@ static hipError_t launch_lane2_t(EnvArgs a, int hb, hipStream_t s)
 // column), 64 below (no more waves to hold; fewer catch-ups and overflows:
 // 256^3 at rel. bound 5e-3, 222 -> 188 us).
 static hipError_t launch_lane2_y(EnvArgs a, int hb, const unsigned long long* b1count, uint32_t* ovf_flag,
-                                 hipStream_t s)
+                                 bool natural, hipStream_t s)
 {
     constexpr int WPB = 4;
     const int64_t nxb = (a.nx + 63) >> 6;
@@ -3138,8 +3140,8 @@ static hipError_t launch_lane2_y(EnvArgs a, int hb, const unsigned long long* b1
     const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
     const dim3 grid(grid_cap(groups, 1u << 20)), blk(64 * WPB);
     if (a.ntiles <= 2048)
-        return launch_checked(k_env_lane2_y<64, WPB>, grid, blk, 0, s, a, hb, b1count, ovf_flag);
-    return launch_checked(k_env_lane2_y<32, WPB>, grid, blk, 0, s, a, hb, b1count, ovf_flag);
+        return launch_checked(k_env_lane2_y<64, WPB>, grid, blk, 0, s, a, hb, b1count, ovf_flag, natural);
+    return launch_checked(k_env_lane2_y<32, WPB>, grid, blk, 0, s, a, hb, b1count, ovf_flag, natural);
 }
 
 template <int AXIS>
@@ -3674,16 +3676,19 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
         ea.win = buf[c2];
         ea.w = buf[nx2];
         int hb = 0;
-        blk = search && t.env_algo[1] == 3 && lane2_geometry(1, ea, hb);
+        const bool lane = t.env_algo[1] == 3 && lane2_geometry(1, ea, hb);
+        blk = search && lane;
         if (blk && fused_edt1(p, t, t_in))
             b1est = (const unsigned long long*)(p.status + QAI_B1_WORD);
         // columns whose envelope outgrows the per-lane ring (sparse B2 over
         // long x-lines) hand the pass to the banded pass, gated on a header word
-        if (blk && p.ny <= 64 * 32)
+        // (ahead of a whole z pass too: the ring size and the hand-off then
+        // serve it as they serve the search)
+        if (lane && p.ny <= 64 * 32)
             ovf = p.status + QAI_OVF_WORD;
         prof_begin("edt2_y", s);
-        if (blk)
-            QAI_TRY(launch_lane2_y(ea, hb, b1est, ovf, s));
+        if (lane)
+            QAI_TRY(launch_lane2_y(ea, hb, b1est, ovf, !blk, s));
         else
             QAI_TRY(launch_env(1, ea, t, s));
         if (ovf) {

@@ -351,8 +351,9 @@ def test_envelope_ring_overflow_hands_the_y_pass_to_the_banded_pass():
     (32 ring entries per lane): some column's live window outgrows the
     per-lane envelope's ring in the second EDT's y pass, the pass raises the
     header word and the banded pass (gated on it) redoes the whole y pass in
-    the natural layout, which the needed-voxel search then reads.  The output
-    matches the tapped call and the oracle."""
+    the natural layout, which the needed-voxel search then reads.  The tapped
+    call (whole z pass) takes the same hand-off ahead of its z pass.  The
+    output matches the tapped call and the oracle."""
     import paper_2602_20097_amd as qai
     x32, xq, q, eb = synth.quantize(synth.grf((130, 128, 1024), 3.7, 77), 1.6e-4)
     t = torch.from_numpy(xq).cuda()
@@ -360,4 +361,8 @@ def test_envelope_ring_overflow_hands_the_y_pass_to_the_banded_pass():
     qai.mitigate(t, eb, workspace=ws)
     torch.cuda.synchronize()
     assert int(ws[68:72].view(torch.int32).item()) != 0  # header word 17: the ring overflowed
+    ws2 = qai.new_workspace(t.shape)
+    qai.mitigate(t, eb, taps=True, workspace=ws2)
+    torch.cuda.synchronize()
+    assert int(ws2[68:72].view(torch.int32).item()) != 0
     assert_parity(xq, eb, label="ring overflow (130, 128, 1024)")
