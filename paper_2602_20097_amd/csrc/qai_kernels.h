@@ -86,7 +86,8 @@ struct EnvArgs {
 #define QAI_WIDE_WORD 16
 #define QAI_OVF_WORD 17
 #define QAI_B1_WORD 18
-#define QAI_HEADER_WORDS 20
+#define QAI_OVFZ_WORD 20 // the same as QAI_OVF_WORD for a whole z pass of the second EDT
+#define QAI_HEADER_WORDS 24
 
 struct InterpArgs {
     const uint32_t* w1;

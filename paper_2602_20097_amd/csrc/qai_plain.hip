@@ -2765,6 +2765,16 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2_y(EnvArgs a, int hb, con
         env_lane2<1, C, WPB, false>(a, hb, ring, stage, ovf_flag);
 }
 
+// A whole z pass of the second EDT by the per-lane envelope, its
+// overflowing columns handed to the banded pass as in k_env_lane2_y.
+template <int C, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_env_lane2_z(EnvArgs a, int hb, uint32_t* ovf_flag)
+{
+    __shared__ uint32_t ring[WPB * C * 64];
+    __shared__ __align__(16) uint32_t stage[4];
+    env_lane2<2, C, WPB, false>(a, hb, ring, stage, ovf_flag);
+}
+
 __global__ void k_clear(uint32_t* p, int n)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -3142,6 +3152,19 @@ static hipError_t launch_lane2_y(EnvArgs a, int hb, const unsigned long long* b1
     if (a.ntiles <= 2048)
         return launch_checked(k_env_lane2_y<64, WPB>, grid, blk, 0, s, a, hb, b1count, ovf_flag, natural);
     return launch_checked(k_env_lane2_y<32, WPB>, grid, blk, 0, s, a, hb, b1count, ovf_flag, natural);
+}
+
+// (ring entries as for the y pass)
+static hipError_t launch_lane2_z(EnvArgs a, int hb, uint32_t* ovf_flag, hipStream_t s)
+{
+    constexpr int WPB = 4;
+    const int64_t nxb = (a.nx + 63) >> 6;
+    a.ntiles = (uint64_t)(nxb * a.ny);
+    const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
+    const dim3 grid(grid_cap(groups, 1u << 20)), blk(64 * WPB);
+    if (a.ntiles <= 2048)
+        return launch_checked(k_env_lane2_z<64, WPB>, grid, blk, 0, s, a, hb, ovf_flag);
+    return launch_checked(k_env_lane2_z<32, WPB>, grid, blk, 0, s, a, hb, ovf_flag);
 }
 
 template <int AXIS>
@@ -3725,8 +3748,20 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
         const int nx2 = (c2 == o0) ? o1 : o0;
         ea.win = buf[c2];
         ea.w = buf[nx2];
+        ea.gate = nullptr;
+        int hb = 0;
         prof_begin("edt2_z", s);
-        QAI_TRY(launch_env(2, ea, t, s));
+        if (t.env_algo[2] == 3 && p.nz <= 64 * 32 && lane2_geometry(2, ea, hb)) {
+            // per-lane envelope with the banded pass behind it for columns
+            // that outgrow the ring
+            uint32_t* ovfz = p.status + QAI_OVFZ_WORD;
+            QAI_TRY(launch_lane2_z(ea, hb, ovfz, s));
+            EnvArgs eg = ea;
+            eg.gate = ovfz;
+            QAI_TRY(launch_band2(2, eg, t, s));
+        } else {
+            QAI_TRY(launch_env(2, ea, t, s));
+        }
         prof_end(s);
         c2 = nx2;
     }
