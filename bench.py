@@ -75,6 +75,8 @@ STAGE_BYTES = {
                           # y-pass words only at the voxels whose weight needs d2, ~3% at 512^3)
     "edt2_z_stream": 12,  # its streaming phase alone, on a side stream beside the y pass
     "edt2_z_search": 0,   # its search phase: reads only at the voxels whose weight needs d2
+    "edt2_z_sparse": 0,   # whole z pass + step E on the side stream, run instead of the search only
+                          # where B1 covers under 60% (launches that return at once elsewhere)
     "edt2_y_interp": 12,  # 2-D: step E fused with the y pass done where the weight needs d2 (read
                           # first-EDT words, x'; write out; x-pass words read by the searches)
     "clear": 0,

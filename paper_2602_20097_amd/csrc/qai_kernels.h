@@ -98,6 +98,7 @@ struct InterpArgs {
     float eta_eb, power;
     int32_t* td2;
     float* tw;
+    const unsigned long long* only_sparse; // when set, runs only where sparse_b1 holds for this estimate
 };
 
 // Launch geometry chosen per pass (the autotuner overrides the defaults).

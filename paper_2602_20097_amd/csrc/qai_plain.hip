@@ -1022,8 +1022,36 @@ __device__ __forceinline__ void interp_store(int64_t i, uint32_t w2word, const u
         tw[i] = wt;
 }
 
+// Where B1 covers less than 60% of the field (the first seed pass's
+// estimate) most voxels need d2 (on 128x128x1024 and 100x500x500 fields at
+// rel. bounds 4e-3..1e-2: 48-81%), and a whole z pass with step E beats the
+// needed-voxel search (0.66-0.98 against 0.98-1.39 ms; at 93% B1 the search
+// wins, 0.65 against 0.76 ms).  The two are launched side by side, each gated
+// on this test.
+__device__ __forceinline__ bool sparse_b1(const unsigned long long* b1count, uint64_t n)
+{
+    return *b1count * 5ull < n * 3ull;
+}
+
+// With only_sparse set the kernel finishes what the needed-voxel search
+// would: voxels with S != 0 off B1 and off B2 (w2 != 0), whose out the
+// streaming phase left at x' (so x' may alias out); every other voxel keeps
+// the streaming phase's value.
 __global__ __launch_bounds__(256) void k_interp(InterpArgs a)
 {
+    if (a.only_sparse) {
+        if (!sparse_b1(a.only_sparse, (uint64_t)a.n))
+            return;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+            const uint32_t w1w = a.w1[i];
+            if (word_sign(w1w) == 0 || w1w == QAI_WORD_INF || word_d2(w1w) == 0u)
+                continue;
+            const uint32_t w2w = a.w2[i];
+            if (w2w != 0u)
+                interp_store(i, w2w, a.w1, a.xq, a.out, a.eta_eb, a.power, nullptr, nullptr);
+        }
+        return;
+    }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x)
         interp_store(i, a.w2[i], a.w1, a.xq, a.out, a.eta_eb, a.power, a.td2, a.tw);
 }
@@ -1060,6 +1088,7 @@ struct ZsArgs {
     const unsigned long long* b1count; // when set, the layout is chosen on the device (blocked_layout)
     const uint32_t* ovf;  // when set and raised, the y pass was redone by the banded pass (natural layout)
     const uint32_t* gx;   // k_interp_pre: the x-pass words of the second EDT (natural layout; w2 holds them)
+    const unsigned long long* skip_sparse; // k_interp_far: when set, returns where sparse_b1 holds
 };
 
 // The y pass of the second EDT hands the needed-voxel search its words in the
@@ -1346,6 +1375,8 @@ __global__ __launch_bounds__(256) void k_interp_far(ZsArgs a, int64_t nwords, Fa
     constexpr int L = FAR_LIST;
     __shared__ int64_t list[L];
     __shared__ int wsum[4];
+    if (a.skip_sparse && sparse_b1(a.skip_sparse, (uint64_t)(a.nx * a.ny * a.nz)))
+        return; // the whole z pass runs instead
     const bool blk = zs_blocked(a);
     const int64_t plane = a.nx * a.ny, gplane = blk ? gy_plane<true>(a) : gy_plane<false>(a);
     const GyReader<BUF> g(a.gy, gplane * a.nz);
@@ -2767,11 +2798,15 @@ __global__ __launch_bounds__(64 * WPB) void k_env_lane2_y(EnvArgs a, int hb, con
 
 // A whole z pass of the second EDT by the per-lane envelope, its
 // overflowing columns handed to the banded pass as in k_env_lane2_y.
+// only_sparse: when set, the pass runs only where sparse_b1 holds.
 template <int C, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_env_lane2_z(EnvArgs a, int hb, uint32_t* ovf_flag)
+__global__ __launch_bounds__(64 * WPB) void k_env_lane2_z(EnvArgs a, int hb, uint32_t* ovf_flag,
+                                                          const unsigned long long* only_sparse)
 {
     __shared__ uint32_t ring[WPB * C * 64];
     __shared__ __align__(16) uint32_t stage[4];
+    if (only_sparse && !sparse_b1(only_sparse, (uint64_t)(a.nx * a.ny * a.nz)))
+        return;
     env_lane2<2, C, WPB, false>(a, hb, ring, stage, ovf_flag);
 }
 
@@ -3155,7 +3190,8 @@ static hipError_t launch_lane2_y(EnvArgs a, int hb, const unsigned long long* b1
 }
 
 // (ring entries as for the y pass)
-static hipError_t launch_lane2_z(EnvArgs a, int hb, uint32_t* ovf_flag, hipStream_t s)
+static hipError_t launch_lane2_z(EnvArgs a, int hb, uint32_t* ovf_flag, const unsigned long long* only_sparse,
+                                 hipStream_t s)
 {
     constexpr int WPB = 4;
     const int64_t nxb = (a.nx + 63) >> 6;
@@ -3163,8 +3199,8 @@ static hipError_t launch_lane2_z(EnvArgs a, int hb, uint32_t* ovf_flag, hipStrea
     const uint64_t groups = (a.ntiles + WPB - 1) / WPB;
     const dim3 grid(grid_cap(groups, 1u << 20)), blk(64 * WPB);
     if (a.ntiles <= 2048)
-        return launch_checked(k_env_lane2_z<64, WPB>, grid, blk, 0, s, a, hb, ovf_flag);
-    return launch_checked(k_env_lane2_z<32, WPB>, grid, blk, 0, s, a, hb, ovf_flag);
+        return launch_checked(k_env_lane2_z<64, WPB>, grid, blk, 0, s, a, hb, ovf_flag, only_sparse);
+    return launch_checked(k_env_lane2_z<32, WPB>, grid, blk, 0, s, a, hb, ovf_flag, only_sparse);
 }
 
 template <int AXIS>
@@ -3439,7 +3475,9 @@ hipError_t launch_env(int axis, EnvArgs a, const Tuning& t, hipStream_t s)
 hipError_t launch_interp(const InterpArgs& a, hipStream_t s)
 {
     const uint64_t blocks = (uint64_t)((a.n + 255) / 256);
-    return launch_checked(k_interp, dim3(grid_cap(blocks, 1u << 20)), dim3(256), 0, s, a);
+    // gated (only_sparse): a small grid, so that a launch that returns at once
+    // costs no dispatch of a block per 256 voxels
+    return launch_checked(k_interp, dim3(grid_cap(blocks, a.only_sparse ? 4096u : 1u << 20)), dim3(256), 0, s, a);
 }
 
 hipError_t launch_clear(uint32_t* p, int n, hipStream_t s)
@@ -3527,6 +3565,14 @@ static SeedArgs seed_args(const Plan1& p)
 // A 3-D field with both passes of the first EDT on automatic takes them as
 // one search over (y, z) (k_edt1_yz); its seed pass (k_seed_lane) then
 // estimates the B1 count, which the later passes read on the device.
+// The first seed pass estimates B1 on 3-D fields whenever it is the
+// register-resident kernel (the fused first-EDT search and the choice between
+// the needed-voxel search and a whole z pass read the estimate).
+static bool b1_estimated(const Plan1& p, const Tuning& t)
+{
+    return p.nz > 1 && p.ny > 1 && t.seed_ty == 0 && p.nx <= kSeedLaneMaxX;
+}
+
 static bool fused_edt1(const Plan1& p, const Tuning& t, const Tuning& t_in)
 {
     return p.nz > 1 && p.ny > 1 && p.nx % 4 == 0 && p.nx <= 512 && t.seed_ty == 0 && t_in.edt1_algo[1] < 0 &&
@@ -3551,7 +3597,7 @@ hipError_t run_part1(Plan1& p, const Tuning& t_in, hipStream_t s, int* w1)
     // either way
     const bool yz = fused_edt1(p, t, t_in);
     unsigned long long* const b1count = (unsigned long long*)(p.status + QAI_B1_WORD);
-    sa.b1count = yz ? b1count : nullptr;
+    sa.b1count = (yz || b1_estimated(p, t)) ? b1count : nullptr;
     int cur = yz ? 1 : 0;
     sa.wout = buf[cur];
     if (p.coded && coded_seed_supported(p.nx) && t.seed_ty == 0) {
@@ -3701,7 +3747,7 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
         int hb = 0;
         const bool lane = t.env_algo[1] == 3 && lane2_geometry(1, ea, hb);
         blk = search && lane;
-        if (blk && fused_edt1(p, t, t_in))
+        if (blk && b1_estimated(p, t))
             b1est = (const unsigned long long*)(p.status + QAI_B1_WORD);
         // columns whose envelope outgrows the per-lane ring (sparse B2 over
         // long x-lines) hand the pass to the banded pass, gated on a header word
@@ -3726,14 +3772,46 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
         // last pass of step D only at needed voxels, fused with step E
         const int nx2 = (c2 == o0) ? o1 : o0;
         ZsArgs za = {buf[w1], buf[c2], buf[nx2], p.xq, p.out, p.flags, p.nx, p.ny, p.nz, p.eta * p.eb, p.power, blk,
-                     b1est, ovf, nullptr};
+                     b1est, ovf, nullptr, nullptr};
         if (overlap) {
             if (nx2 != o0)
                 return hipErrorInvalidValue; // the streaming phase relied on w2 being the x-pass buffer
             QAI_TRY(hipStreamWaitEvent(s, p.aux->join, 0));
+            // with the B1 estimate at hand, the whole z pass and step E at the
+            // voxels the search would take go to the side stream beside the
+            // search, each gated on sparse_b1
+            EnvArgs ez = ea;
+            ez.win = buf[c2];
+            ez.w = buf[nx2];
+            ez.gate = nullptr;
+            int hbz = 0;
+            const unsigned long long* b1all = (const unsigned long long*)(p.status + QAI_B1_WORD);
+            // (passes of at most 2048 column tiles: on larger ones the gated
+            // envelope's blocks, which hold its LDS ring, wait beside the
+            // search's and delay it even when they return at once: 512^3
+            // 1.600 -> 1.614 ms)
+            const bool dual = b1_estimated(p, t) && p.nz <= 64 * 32 && ((p.nx + 63) / 64) * p.ny <= 2048 &&
+                              lane2_geometry(2, ez, hbz);
+            if (dual) {
+                // (no banded pass behind it: its gated launch would wait for
+                // LDS behind the search's blocks; overflowing columns take the
+                // envelope kernel's own exact outward search)
+                QAI_TRY(hipEventRecord(p.aux->fork, s));
+                QAI_TRY(hipStreamWaitEvent(p.aux->s, p.aux->fork, 0));
+                prof_begin("edt2_z_sparse", p.aux->s);
+                QAI_TRY(launch_lane2_z(ez, hbz, nullptr, b1all, p.aux->s));
+                InterpArgs ia = {buf[w1], buf[nx2], p.xq, p.out, p.nx * p.ny * p.nz, p.eta * p.eb, p.power, nullptr,
+                                 nullptr, b1all};
+                QAI_TRY(launch_interp(ia, p.aux->s));
+                prof_end(p.aux->s);
+                QAI_TRY(hipEventRecord(p.aux->join, p.aux->s));
+                za.skip_sparse = b1all;
+            }
             prof_begin("edt2_z_search", s);
             QAI_TRY(launch_interp_far(za, t.force_wide != 0, s));
             prof_end(s);
+            if (dual)
+                QAI_TRY(hipStreamWaitEvent(s, p.aux->join, 0));
         } else {
             prof_begin("edt2_z_interp", s);
             QAI_TRY(launch_interp_stream(za, t.force_wide != 0, false, s));
@@ -3755,7 +3833,7 @@ hipError_t run_part2(Plan1& p, const Tuning& t_in, hipStream_t s, int w1)
             // per-lane envelope with the banded pass behind it for columns
             // that outgrow the ring
             uint32_t* ovfz = p.status + QAI_OVFZ_WORD;
-            QAI_TRY(launch_lane2_z(ea, hb, ovfz, s));
+            QAI_TRY(launch_lane2_z(ea, hb, ovfz, nullptr, s));
             EnvArgs eg = ea;
             eg.gate = ovfz;
             QAI_TRY(launch_band2(2, eg, t, s));

@@ -31,6 +31,7 @@ STAGES = [
     (r"k_interp_pre", "edt2_z_stream"),
     (r"k_interp_far", "edt2_z_search"),
     (r"k_interp_dir", "edt2_y_interp"),
+    (r"k_env_lane2_z", "edt2_z_sparse"),
     (r"k_edt1_yz", "edt1_yz"),
     (r"k_env_lane2_y\b", "edt2_y"),
     (r"k_interp\b", "interp"),
