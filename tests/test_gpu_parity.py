@@ -368,11 +368,14 @@ def test_envelope_ring_overflow_hands_the_y_pass_to_the_banded_pass():
     assert_parity(xq, eb, label="ring overflow (130, 128, 1024)")
 
 
-def test_sparse_b1_takes_the_whole_z_pass_beside_the_search():
-    """Where B1 covers under 60% of the field most voxels need d2, and the
-    whole z pass with step E runs on the side stream instead of the
-    needed-voxel search (both are launched, each gated on the first seed
-    pass's B1 estimate): the output matches the tapped call and the oracle."""
-    x32, xq, q, eb = synth.quantize(synth.grf((64, 128, 192), 3.0, 17), 2e-2)
-    g, r = assert_parity(xq, eb, label="sparse B1, whole z pass")
+@pytest.mark.parametrize("shape", [(64, 128, 192), (8, 300, 512)])
+def test_sparse_b1_takes_the_whole_z_pass_beside_the_search(shape):
+    """Where B1 covers under 60% of the field most voxels need d2, and on z
+    passes of at most 2048 column tiles (64 x 128 x 192: 384) the whole z pass
+    with step E runs on the side stream instead of the needed-voxel search
+    (both are launched, each gated on the first seed pass's B1 estimate); on
+    larger ones (8 x 300 x 512: 2400) the search runs alone.  Either way the
+    output matches the tapped call and the oracle."""
+    x32, xq, q, eb = synth.quantize(synth.grf(shape, 3.0, 17), 2e-2)
+    g, r = assert_parity(xq, eb, label=f"sparse B1 {shape}")
     assert r["b1"].mean() < 0.55
