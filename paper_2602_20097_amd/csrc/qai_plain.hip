@@ -2581,6 +2581,10 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
         uint32_t eoff = vo, poff = vo, pval = QAI_WORD_INF;
         bool ovf = false;
 
+        // (the loop tests below evaluate both operands, no short circuit: the
+        // second reads entries outside the live window once the first fails,
+        // whose values are then unused, and a branch per test costs more
+        // scalar and branch instructions than the arithmetic it skips)
         // the owner of row e: step while the next entry is strictly better
         // (24-bit products: lane2_geometry keeps lines below 1024 rows, so
         // 2 e dfh and e (e - 2 fh0) fit; a 32-bit multiply costs four times as
@@ -2588,7 +2592,7 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
         // sign extension of its operands)
         auto walk = [&]() {
             const int e2 = 2 * e;
-            if (lo < top && dfc < (int)__umul24((uint32_t)e2, (uint32_t)dfh)) {
+            if ((lo < top) & (dfc < (int)__umul24((uint32_t)e2, (uint32_t)dfh))) {
 #pragma unroll 1
                 do {
                     ++lo;
@@ -2597,7 +2601,7 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
                     dfc = (int)(f2p >> hb) - fc0;
                     dfh = (int)(f2p & hm) - fh0;
                     f2p = rl[SLOT(lo + 2)];
-                } while (lo < top && dfc < (int)__umul24((uint32_t)e2, (uint32_t)dfh));
+                } while ((lo < top) & (dfc < (int)__umul24((uint32_t)e2, (uint32_t)dfh)));
             }
             be = (uint32_t)(fc0 + __mul24(e, e - 2 * fh0));
         };
@@ -2612,7 +2616,7 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
             if ((w != QAI_WORD_INF) & !ovf) { // one branch for both conditions
                 const int g = (int)(w >> 2);
                 const int cw = g + i * i;
-                bool rm = top > lo && __mul24(dc, i - h0) - __mul24(cw - c0, dh) > 0;
+                bool rm = (top > lo) & (__mul24(dc, i - h0) > __mul24(cw - c0, dh));
 #pragma unroll 1
                 while (rm) {
                     --top;
@@ -2621,7 +2625,7 @@ __device__ __forceinline__ void env_lane2(const EnvArgs& a, int hb, uint32_t* ri
                     dc = c0 - (int)(t2p >> hb);
                     dh = h0 - (int)(t2p & hm);
                     t2p = rl[SLOT(top - 2)];
-                    rm = top > lo && __mul24(dc, i - h0) - __mul24(cw - c0, dh) > 0;
+                    rm = (top > lo) & (__mul24(dc, i - h0) > __mul24(cw - c0, dh));
                 }
                 ovf = top - lo + 1 >= C;
                 t2p = rl[SLOT(top - 1)];
